@@ -1,0 +1,161 @@
+"""Pins of the oracle's amplitude solve (Sec. 4.1, dchi2/dI0 = 0), chi^2
+gradient, and profile fit (Sec. 4.1; Levenberg-Marquardt in place of MINUIT)."""
+import numpy as np
+import pytest
+from scipy import optimize
+
+import oracle
+import synth
+
+
+def test_linear_amplitudes_match_lstsq():
+    rng = np.random.default_rng(3)
+    p = np.array([20.3, 21.1, 0.2, -0.1, 3.1, 1.7, 1.0, 0.0])
+    f = oracle.model(42, p)
+    img = 311.0 * f + 9.5 + rng.normal(0, 2.0, f.shape)
+    a, c = oracle.linear(img, p)
+    X = np.stack([f.ravel(), np.ones(f.size)], 1)
+    ref = np.linalg.lstsq(X, img.ravel(), rcond=None)[0]
+    assert a == pytest.approx(ref[0], rel=1e-11)
+    assert c == pytest.approx(ref[1], rel=1e-11)
+
+
+@pytest.mark.parametrize("kind", [oracle.SERSIC, oracle.MOFFAT])
+def test_chi2_gradient_and_jtj(kind):
+    b = synth.make("plain48", count=4)
+    for s in range(b.n):
+        img = b.stamp(s)
+        sg = float(b.sigma[s])
+        p = b.truth[s].copy()
+        if kind == oracle.MOFFAT:
+            p[4], p[5] = 2.2, 3.4
+        p *= np.array([1.0, 1.0, 0.9, 1.1, 1.15, 0.9, 1.2, 1.01])
+        p[0] += 0.3
+        c2, g, jtj = oracle.chi2(img, sg, p, kind=kind, want_grad=True)
+        scale = np.array([1, 1, 1, 1, p[4], p[5], abs(p[6]), sg])
+        for k in range(8):
+            h = 1e-5 * scale[k]
+            dp = np.zeros(8)
+            dp[k] = h
+            fd = (oracle.chi2(img, sg, p + dp, kind=kind) - oracle.chi2(img, sg, p - dp, kind=kind)) / (2 * h)
+            assert g[k] == pytest.approx(fd, rel=1e-6, abs=1e-6 * abs(c2) / scale[k])
+        _, J = oracle.model(48, p, kind=kind, jac=True)
+        Jf = J.reshape(-1, 8) / sg
+        full = Jf.T @ Jf
+        iu = np.triu_indices(8)
+        np.testing.assert_allclose(jtj, full[iu], rtol=1e-10, atol=1e-12 * np.abs(full).max())
+
+
+def _noiseless(p, side, kind=oracle.SERSIC):
+    r = synth.render_sersic if kind == oracle.SERSIC else synth.render_moffat
+    return r(side, p)[0] + p[7]
+
+
+@pytest.mark.parametrize("truth", [
+    (23.7, 24.2, 0.21, -0.13, 3.2, 0.7, 500.0, 10.0),
+    (22.9, 23.1, -0.35, 0.30, 4.5, 1.6, 80.0, 10.0),
+    (24.4, 23.0, 0.05, 0.55, 2.6, 3.4, 2000.0, 10.0),
+])
+def test_noiseless_recovery_8_params(truth):
+    truth = np.array(truth)
+    img = _noiseless(truth, 48)
+    p0 = truth * np.array([1, 1, 0.8, 1.2, 1.25, 0.8, 1, 1]) + np.array([0.4, -0.3, 0, 0, 0, 0, 0, 0])
+    r = oracle.fit(img, 1.0, p0, o=oracle.opts(tol_lm=1e-12, max_iter_lm=300))
+    assert r["status"] & oracle.CONVERGED
+    np.testing.assert_allclose(r["p"][:4], truth[:4], atol=1e-7)
+    np.testing.assert_allclose(r["p"][4:], truth[4:], rtol=1e-7)
+    assert r["chi2"] < 1e-12
+
+
+def test_noiseless_recovery_moffat():
+    truth = np.array([31.2, 30.7, 0.06, -0.04, 2.4, 3.0, 900.0, 10.0])
+    img = _noiseless(truth, 64, oracle.MOFFAT)
+    p0 = truth * np.array([1, 1, 0.5, 0.5, 1.3, 1, 1, 1]) + np.array([0.3, 0.2, 0, 0, 0, 0, 0, 0])
+    r = oracle.fit(img, 1.0, p0, kind=oracle.MOFFAT, o=oracle.opts(tol_lm=1e-12, max_iter_lm=300))
+    assert r["status"] & oracle.CONVERGED
+    np.testing.assert_allclose(r["p"], truth, rtol=1e-7, atol=1e-7)
+
+
+def test_brute_force_two_parameter_minimum():
+    """Tiny stamps: the 4-parameter fit (Re, n with I0, sky linear; the paper's
+    split) equals a dense grid + Nelder-Mead search of the profiled chi^2."""
+    rng = np.random.default_rng(11)
+    side = 12
+    for trial in range(4):
+        truth = np.array([5.6 + 0.3 * trial, 5.4, 0.1, -0.2 + 0.1 * trial, 2.0 + 0.3 * trial,
+                          0.8 + 0.5 * trial, 1500.0, 10.0])
+        sg = 4.0
+        img = _noiseless(truth, side) + rng.normal(0, sg, (side, side))
+
+        def prof(x):
+            re, n = x
+            if not (0.1 <= re <= side and 0.2 <= n <= 10):
+                return 1e30
+            q = truth.copy()
+            q[4], q[5], q[6], q[7] = re, n, 1.0, 0.0
+            f = oracle.model(side, q).ravel()
+            X = np.stack([f, np.ones_like(f)], 1)
+            coef, *_ = np.linalg.lstsq(X, img.ravel(), rcond=None)
+            return float(((img.ravel() - X @ coef) ** 2).sum()) / sg ** 2
+
+        res, ns = np.linspace(0.6, 6, 40), np.linspace(0.3, 6, 40)
+        vals = np.array([[prof((a, c)) for c in ns] for a in res])
+        ia, ic = np.unravel_index(np.argmin(vals), vals.shape)
+        assert 0 < ia < len(res) - 1 and 0 < ic < len(ns) - 1   # interior minimum
+        bf = optimize.minimize(prof, [res[ia], ns[ic]], method="Nelder-Mead",
+                               options=dict(xatol=1e-10, fatol=1e-13, maxiter=4000))
+        p0 = truth.copy()
+        p0[4], p0[5] = res[ia], ns[ic]
+        r = oracle.fit(img, sg, p0, o=oracle.opts(free_mask=0xF0, tol_lm=1e-12, max_iter_lm=500))
+        assert r["status"] & oracle.CONVERGED
+        assert r["chi2"] == pytest.approx(bf.fun, rel=1e-9)
+        np.testing.assert_allclose(r["p"][4:6], bf.x, rtol=2e-5)
+
+
+def test_fit_is_stationary_point_of_full_chi2():
+    """Profiling (I0, sky) out does not change the minimum: all 8 components
+    of the full chi^2 gradient vanish at the result."""
+    b = synth.make("plain48", count=24)
+    r = oracle.pipeline(b)
+    checked = 0
+    for s in range(b.n):
+        if not r["status"][s, 2] & oracle.CONVERGED:
+            continue
+        p = r["p"][s]
+        if not (0.2 < p[4] < 47 and 0.3 < p[5] < 9.5 and np.hypot(p[2], p[3]) < 0.9):
+            continue                      # a minimum on the box boundary is not stationary
+        sg = float(b.sigma[s])
+        c2, g, _ = oracle.chi2(b.stamp(s), sg, p, want_grad=True)
+        scale = np.array([1, 1, 1, 1, p[4], p[5], abs(p[6]), sg])
+        # gradient in units of chi^2 per unit of relative parameter change
+        assert np.abs(g * scale).max() < 1e-4
+        checked += 1
+    assert checked >= 18
+
+
+def test_reduced_chi2_near_one_and_covariance():
+    b = synth.make("plain48", count=200)
+    r = oracle.pipeline(b)
+    ok = (r["status"][:, 2] & oracle.CONVERGED) != 0
+    red = r["chi2"][ok] / (48 * 48 - 8)
+    assert abs(red.mean() - 1.0) < 4 * np.sqrt(2.0 / (48 * 48)) / np.sqrt(ok.sum()) + 2e-3
+    s = int(np.flatnonzero(ok)[0])
+    fr = oracle.fit(b.stamp(s), float(b.sigma[s]), r["p"][s])
+    _, J = oracle.model(48, fr["p"], jac=True)
+    Jf = J.reshape(-1, 8) / float(b.sigma[s])
+    cov = np.linalg.inv(Jf.T @ Jf)
+    np.testing.assert_allclose(fr["perr"], np.sqrt(np.diag(cov)), rtol=1e-8)
+
+
+def test_gaussian_workload_pipeline():
+    """The 1,000-stamp Gaussian workload: every stage converges for nearly all
+    stamps and the recovered shapes scatter around the truth."""
+    b = synth.make("plain32")
+    r = oracle.pipeline(b, oracle.opts(free_mask=0xF0))
+    conv = (r["status"][:, 2] & oracle.CONVERGED) != 0
+    assert conv.mean() > 0.99
+    assert ((r["status"][:, 1] & oracle.CONVERGED) != 0).mean() > 0.99
+    d = r["p"][conv] - b.truth[conv]
+    assert np.median(np.abs(d[:, 0])) < 0.05
+    assert np.median(np.abs(d[:, 2:4])) < 0.02
+    assert np.median(np.abs(r["p"][conv, 5] / 0.5 - 1)) < 0.05

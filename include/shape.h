@@ -1,0 +1,182 @@
+/*
+ * libshape: batched shape measurement of galaxies and stars on AMD MI355X
+ * (gfx950), after Li, Xin & Cui (2012), "Fast Shape Estimation for Galaxies
+ * and Stars" (arXiv:1203.0571).
+ *
+ * Three stages, each one call over a batch of square postage stamps:
+ *   shape_centroid    starting estimates and the Gaussian-weighted centroid
+ *                     (Sec. 2; starting point of Sec. 4.1)
+ *   shape_moments     joint centroid + ellipticity with an elliptical weight
+ *                     (Sec. 3, App. A, App. B)
+ *   shape_fit_sersic  chi^2 fit of the remaining profile parameters with the
+ *                     amplitudes solved analytically (Sec. 4.1, eqs. ser,
+ *                     chi2 and the dchi2/dI0 = 0 normalisation)
+ * plus the chi^2 of a given parameter set and its gradient (for automatic
+ * differentiation and for driving the fit from outside).
+ *
+ * Conventions
+ *   - Stamps are square, side W in [4, 128], row-major; pixel (row i, col j)
+ *     has centre (x, y) = (j, i).
+ *   - Parameters p = (x0, y0, e1, e2, Re, n, I0, sky).  The model is
+ *       u = (x - x0, y - y0),  v = S(e) u,  S(e) = [[1-e1, -e2], [-e2, 1+e1]],
+ *       R^2 = max(|v|^2 / (1 - |e|^2), 1e-8),
+ *       Sersic: m = I0 exp(-b(n) (R/Re)^(1/n)) + sky, b(n) the half-light
+ *               constant (P(2n, b) = 1/2);
+ *       Moffat (stars, model = 1): m = I0 (1 + R^2/rd^2)^(-beta) + sky with
+ *               rd in slot 4 and beta in slot 5 (held fixed).
+ *     (e1, e2) is the reduced-shear ellipticity g of the paper:
+ *     |e| = (a - b)/(a + b); e1 > 0 is elongated along x, e2 > 0 along y = x.
+ *     Re is the circularised half-light radius.
+ *   - All arrays passed to the stage calls are DEVICE pointers owned by the
+ *     caller; the library allocates nothing.  Calls are asynchronous on
+ *     `stream` (a hipStream_t; NULL = the default stream): SHAPE_OK means the
+ *     work was enqueued, outputs are valid after the stream is synchronised.
+ *   - Host-checkable argument errors return SHAPE_EINVAL before any launch;
+ *     HIP launch errors return SHAPE_EDEVICE.  Problems with one stamp (side
+ *     out of range, sigma <= 0, offset outside the pixel buffer, NaN/Inf
+ *     pixels) never fail the call: they set that stamp's status bits and its
+ *     outputs to NaN.  n = 0 is a no-op returning SHAPE_OK.
+ *   - Reentrant; no global mutable state.
+ */
+#ifndef SHAPE_H
+#define SHAPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHAPE_ABI_VERSION 1
+
+typedef enum {
+  SHAPE_OK = 0,
+  SHAPE_EINVAL = -1,       /* bad argument (checked on the host) */
+  SHAPE_EDEVICE = -2,      /* HIP API or launch failure */
+  SHAPE_ENOMEM = -3,       /* workspace too small */
+  SHAPE_EUNSUPPORTED = -4  /* valid but not implemented (e.g. a free mask) */
+} shape_status;
+
+typedef enum { SHAPE_F32 = 0, SHAPE_F16_SCALED = 1 } shape_dtype;
+typedef enum { SHAPE_SERSIC = 0, SHAPE_MOFFAT = 1 } shape_model;
+
+/* Per-stamp status bits (uint32 per stamp and stage). */
+#define SHAPE_ST_CONVERGED        0x001u /* stopping rule met */
+#define SHAPE_ST_MAX_ITER         0x002u /* iteration cap reached */
+#define SHAPE_ST_STALLED          0x004u /* LM damping exceeded 1e10 */
+#define SHAPE_ST_SINGULAR         0x008u /* a 2x2 or normal-equation solve failed */
+#define SHAPE_ST_NONFINITE_INPUT  0x010u /* NaN/Inf pixel */
+#define SHAPE_ST_NONPOSITIVE_FLUX 0x020u /* total or weighted flux <= 0, or I0 <= 0 */
+#define SHAPE_ST_AT_BOUND         0x040u /* an LM trial left the parameter box */
+#define SHAPE_ST_G_CLAMPED        0x080u /* an ellipticity step was halved */
+#define SHAPE_ST_BAD_INPUT        0x100u /* side, sigma, model or offset invalid */
+#define SHAPE_ST_LOST             0x200u /* the centre left the stamp */
+
+/* Per-stamp record written by shape_centroid and shape_moments (8 floats). */
+enum {
+  SHAPE_REC_X0 = 0, SHAPE_REC_Y0 = 1, SHAPE_REC_E1 = 2, SHAPE_REC_E2 = 3,
+  SHAPE_REC_SIGW = 4, SHAPE_REC_R50 = 5, SHAPE_REC_SKY0 = 6, SHAPE_REC_FLUX = 7,
+  SHAPE_REC_LEN = 8
+};
+
+typedef struct {
+  const void*    pixels;   /* device: packed stamps (float, or _Float16 x scale) */
+  const int64_t* offset;   /* device [n]: element offset of each stamp; NULL =>
+                              stamp i starts at i * side0 * side0 */
+  const int32_t* side;     /* device [n]: side of each stamp; NULL => side0 */
+  const float*   scale;    /* device [n]: dequantisation scale (F16 only) */
+  const float*   sigma;    /* device [n]: i.i.d. pixel noise sigma, > 0 */
+  const uint8_t* model;    /* device [n]: shape_model; NULL => all Sersic */
+  int64_t        n;        /* number of stamps, >= 0 */
+  int64_t        n_pixels; /* elements in `pixels` (every stamp must lie inside) */
+  int32_t        side0;    /* uniform side when `side` is NULL */
+  int32_t        dtype;    /* shape_dtype */
+} shape_batch;
+
+typedef struct {
+  int32_t  max_iter_centroid; /* centroid steps (Sec. 4.1: 20) */
+  int32_t  max_iter_moments;  /* joint centroid + ellipticity steps (20) */
+  int32_t  max_iter_lm;       /* LM trials, every trial counts (30) */
+  uint32_t free_mask;         /* bit k => p[k] fitted; 0xFF all eight, 0xF0 =
+                                 (Re, n, I0, sky) with centre and e held */
+  double   k_gain;            /* centroid gain k (Sec. 2: 0.75) */
+  double   tol_x;             /* centroid stop: max |step| in px (1e-4) */
+  double   tol_g;             /* ellipticity stop: max |dg_i| (1e-5) */
+  double   gmax;              /* bound on |g_w| and |e| (0.95) */
+  double   tol_lm;            /* LM stop: accepted step max_k |d_k|/s_k (1e-5),
+                                 s = (1, 1, 1, 1, Re, n) */
+  double   lambda0;           /* initial Marquardt damping (1e-3) */
+  double   chi2_rtol;         /* accept a trial if chi2' <= chi2 (1 + rtol) (1e-6) */
+  double   n0;                /* starting Sersic index (1) */
+  double   moffat_beta;       /* fixed Moffat index (3) */
+  int32_t  linear_init;       /* 1: solve free (I0, sky) linearly at every point */
+  int32_t  reserved;
+} shape_opts;
+
+/* Fill `opts` with the defaults above.  Returns SHAPE_EINVAL if opts is NULL. */
+int shape_default_opts(shape_opts* opts);
+
+/* Static description of a status code (never NULL). */
+const char* shape_status_string(int code);
+
+/* ABI version of the loaded library (SHAPE_ABI_VERSION). */
+int shape_abi_version(void);
+
+/*
+ * Starting estimates and circular-weight centroid (Sec. 2; Sec. 4.1 starting
+ * point).  Per stamp: sky0 = mean of the border pixels; the brightest pixel
+ * (lowest index on ties); r50 = first crossing of half the total sky-subtracted
+ * flux by the growth curve over integer-radius rings about that pixel, linearly
+ * interpolated; sigma_w = clamp(r50 / sqrt(2 ln 2), 1, W/4); then from the
+ * brightest pixel, steps centre += (sum f W theta) / (k sum f W) with
+ * W = exp(-|theta|^2 / 2 sigma_w^2), f = I - sky0, until both steps are below
+ * tol_x or max_iter_centroid steps.
+ *   rec    [n][8] out: x0, y0, 0, 0, sigma_w, r50, sky0, total flux
+ *   iters  [n] out, status [n] out (SHAPE_ST_*)
+ */
+int shape_centroid(const shape_batch* batch, const shape_opts* opts, float* rec,
+                   int32_t* iters, uint32_t* status, void* stream);
+
+/*
+ * Joint centroid + ellipticity (Sec. 3, App. A, App. B).  From g_w = 0 and
+ * the centroid in rec_in, each step forms the elliptical-weight moments
+ * (weight W(R^2) with R^2 = |S(g_w) theta|^2, App. A), the polarisability
+ * P = X^SH + dX^SH - e_obs (x) (e^SH + de^SH), and updates
+ * g_w += (1 - |g_w|^2) P^-1 (e_obs - 2 g_w / (1 + |g_w|^2)) (eq. newg),
+ * halving the step while |g_w| > gmax, and centre += (sum f W theta)/(k sum f W).
+ * Stops when the centre moves less than tol_x and g_w less than tol_g in a
+ * step that was not halved.
+ *   rec_in  [n][8] in (from shape_centroid), rec_out [n][8] out:
+ *           x0, y0, e1, e2, sigma_w, r50, sky0, flux
+ *   iters, status [n] out.  rec_in == rec_out is allowed.
+ */
+int shape_moments(const shape_batch* batch, const shape_opts* opts, const float* rec_in,
+                  float* rec_out, int32_t* iters, uint32_t* status, void* stream);
+
+/*
+ * Profile fit (Sec. 4.1).  Minimises chi^2 = sum ((m - I)/sigma)^2 over the
+ * parameters in free_mask by Levenberg-Marquardt; free amplitudes (I0, sky)
+ * are set to their linear optimum at every evaluated point (the dchi2/dI0 = 0
+ * condition), the step solves (M + lambda diag M) d = J_N^T r with M the Schur
+ * complement of the amplitude block of J^T J, in FP64 on the device.  Moffat
+ * stamps (model = 1) are fitted with beta fixed at opts->moffat_beta.
+ *   p_init [n][8] in, or NULL: start from rec (x0, y0, e1, e2 of the moments,
+ *          Re = r50 (Moffat rd = r50 / sqrt(2^(1/beta) - 1)), n = n0)
+ *   rec    [n][8] in (from shape_moments), used when p_init is NULL
+ *   p_out  [n][8] out; chi2 [n] out; perr [n][8] out or NULL (sqrt of the
+ *          diagonal of (J^T J / sigma^2)^-1 over the fitted parameters)
+ *   iters, status [n] out; iters counts LM trials (every trial counts).
+ *   sweeps [n] out or NULL: pixel sweeps done (the starting point's plus one
+ *          per trial that passed the box check; the amplitude-only start
+ *          sweep is not counted) -- the unit of work for throughput figures.
+ * Returns SHAPE_EUNSUPPORTED for free masks other than 0xFF and 0xF0.
+ */
+int shape_fit_sersic(const shape_batch* batch, const shape_opts* opts, const float* p_init,
+                     const float* rec, float* p_out, float* chi2, float* perr,
+                     int32_t* iters, uint32_t* status, int32_t* sweeps, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHAPE_H */

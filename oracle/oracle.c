@@ -366,7 +366,8 @@ void orc_ksb_terms(const double* img, int side, double sky0, double sigw,
 /* same elliptical weight.  Reading: a step that would take |g_w| past gmax  */
 /* is halved until it does not (the undamped iteration can leave the unit    */
 /* disk for |g| near 0.7).  Stop when the centre moves less than tol_x and   */
-/* g_w less than tol_g, or after max_iter_moments steps.                     */
+/* g_w less than tol_g in a step that was not halved, or after              */
+/* max_iter_moments steps.                                                  */
 /* ------------------------------------------------------------------------ */
 void orc_moments(const double* img, int side, double sky0, double sigw, double r50,
                  double x_in, double y_in, const orc_opts* o, double* out,
@@ -392,10 +393,12 @@ void orc_moments(const double* img, int side, double sky0, double sigw, double r
     double dg1 = (1.0 - gg) * (P22 * r1 - P12 * r2) / det;
     double dg2 = (1.0 - gg) * (-P21 * r1 + P11 * r2) / det;
     double h = 1.0;
+    int halved = 0;
     for (int k = 0; k < 60; ++k) {
       double a = g[0] + h * dg1, b = g[1] + h * dg2;
       if (a * a + b * b <= o->gmax * o->gmax) break;
       h *= 0.5;
+      halved = 1;
       *status |= ORC_G_CLAMPED;
     }
     dg1 *= h;
@@ -406,7 +409,10 @@ void orc_moments(const double* img, int side, double sky0, double sigw, double r
     xc += dx;
     yc += dy;
     if (xc < 0.0 || yc < 0.0 || xc > side - 1 || yc > side - 1) { *status |= ORC_LOST; break; }
-    if (fabs(dx) < o->tol_x && fabs(dy) < o->tol_x && fabs(dg1) < o->tol_g && fabs(dg2) < o->tol_g) {
+    /* a halved step says nothing about convergence (it is small because it
+     * was cut at the |g_w| bound), so it never ends the iteration */
+    if (!halved && fabs(dx) < o->tol_x && fabs(dy) < o->tol_x && fabs(dg1) < o->tol_g &&
+        fabs(dg2) < o->tol_g) {
       *status |= ORC_CONVERGED;
       break;
     }

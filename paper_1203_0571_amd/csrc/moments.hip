@@ -1,0 +1,212 @@
+// Joint centroid + ellipticity with an elliptical Gaussian weight (one wave
+// per stamp): Sec. 3 (eqs. psh, newg), App. A (eqs. xshew, eshew), App. B
+// (eqs. dxsh, desh, P1..P6).
+//
+// Every integrand of App. A and App. B is a polynomial of degree <= 4 in the
+// offsets theta times f W (W' = -W / 2 sigma_w^2), so one sweep per step
+// accumulates the eleven weighted moments
+//   M_pq = sum f W theta1^p theta2^q,  (p, q) in {00, 10, 01, 20, 11, 02,
+//                                                 40, 31, 22, 13, 04}
+// and the 2x2 algebra is done from them in FP64.  The zeroth, first and
+// second moments (which fix the centroid and e_obs, hence the fixed point)
+// are accumulated in FP64; the fourth moments (which only enter the step
+// matrix P) in FP32.
+#include "kernels.hpp"
+
+namespace shape {
+namespace {
+
+struct Mom {
+  double m00, m10, m01, m20, m11, m02;
+  float m40, m31, m22, m13, m04;
+};
+
+// KSB quantities from the moments (weight ellipticity g, W' = c W).
+struct Ksb {
+  double T, e1, e2, P11, P12, P21, P22;
+};
+
+__device__ inline Ksb ksb_from_moments(const Mom& M, double g1, double g2, double c) {
+  const double gg = g1 * g1 + g2 * g2;
+  const double A = 1.0 + gg - 2.0 * g1, B = 1.0 + gg + 2.0 * g1;
+  const double m40 = M.m40, m31 = M.m31, m22 = M.m22, m13 = M.m13, m04 = M.m04;
+  const double tr = M.m20 + M.m02;
+  Ksb k;
+  k.T = tr;
+  const double iT = 1.0 / tr;
+  k.e1 = (M.m20 - M.m02) * iT;
+  k.e2 = 2.0 * M.m11 * iT;
+  // App. A: X^SH and the integral part of e^SH.
+  const double X11 = (2.0 * tr + 2.0 * c * (A * m40 - (A + B) * m22 + B * m04)) * iT;
+  const double X12 = 2.0 * c * ((A + B) * (m31 - m13) - 2.0 * g2 * (m40 - m04)) * iT;
+  const double X21 = 4.0 * c * (A * m31 - B * m13) * iT;
+  const double X22 = (2.0 * tr + 4.0 * c * ((A + B) * m22 - 2.0 * g2 * (m31 + m13))) * iT;
+  const double E1 = 2.0 * k.e1 + 2.0 * c * (A * (m40 + m22) - B * (m22 + m04)) * iT;
+  const double E2 = 2.0 * k.e2 +
+                    2.0 * c * ((A + B) * (m31 + m13) - 2.0 * g2 * (m40 + 2.0 * m22 + m04)) * iT;
+  // App. B: sums of f P1 .. f P6.
+  const double d20 = M.m20 - M.m02;
+  const double P1 = 4.0 * d20 + 2.0 * c * (A * m40 + (B - A) * m22 - B * m04 - 4.0 * g2 * (m31 - m13));
+  const double P2 = 4.0 * M.m11 + 2.0 * c * ((A - B) * (m31 - m13) + 2.0 * g2 * (m40 - 2.0 * m22 + m04));
+  const double P3 = 8.0 * M.m11 + 4.0 * c * (A * m31 + B * m13 - 4.0 * g2 * m22);
+  const double P4 = -2.0 * d20 + 4.0 * c * ((A - B) * m22 + 2.0 * g2 * (m31 - m13));
+  const double P5 = 4.0 * tr + 2.0 * c * (A * (m40 + m22) + B * (m22 + m04) - 4.0 * g2 * (m31 + m13));
+  const double P6 = 2.0 * c * ((A - B) * (m31 + m13) + 2.0 * g2 * (m40 - m04));
+  const double dX11 = (-g1 * P1 - g2 * P2) * iT, dX12 = (g1 * P2 - g2 * P1) * iT;
+  const double dX21 = (-g1 * P3 - g2 * P4) * iT, dX22 = (g1 * P4 - g2 * P3) * iT;
+  const double dE1 = (-g1 * P5 - g2 * P6) * iT, dE2 = (g1 * P6 - g2 * P5) * iT;
+  // eq. psh with the App. B terms: P_ab = X_ab + dX_ab - e_a (e^SH_b + de^SH_b)
+  k.P11 = X11 + dX11 - k.e1 * (E1 + dE1);
+  k.P12 = X12 + dX12 - k.e1 * (E2 + dE2);
+  k.P21 = X21 + dX21 - k.e2 * (E1 + dE1);
+  k.P22 = X22 + dX22 - k.e2 * (E2 + dE2);
+  return k;
+}
+
+template <int DT>
+__global__ __launch_bounds__(kWave) void moments_kernel(shape_batch b, KOpts o, const float* rec_in,
+                                                        float* rec_out, int32_t* iters,
+                                                        uint32_t* status) {
+  const int lane = threadIdx.x;
+  for (int64_t s = blockIdx.x; s < b.n; s += gridDim.x) {
+    const Stamp st = stamp_info(b, s);
+    const float* in = rec_in + s * SHAPE_REC_LEN;
+    float* out = rec_out + s * SHAPE_REC_LEN;
+    // Read the whole input record before anything is written (in == out allowed).
+    float r_in[SHAPE_REC_LEN];
+#pragma unroll
+    for (int q = 0; q < SHAPE_REC_LEN; ++q) r_in[q] = in[q];
+    bool bad_rec = false;
+#pragma unroll
+    for (int q = 0; q < SHAPE_REC_LEN; ++q) bad_rec |= !__builtin_isfinite(r_in[q]);
+    if (st.bad || bad_rec) {
+      __syncthreads();
+      if (lane < SHAPE_REC_LEN) out[lane] = qnan();
+      if (lane == 0) {
+        iters[s] = 0;
+        status[s] = st.bad ? st.bad : SHAPE_ST_BAD_INPUT;
+      }
+      continue;
+    }
+    const int W = st.side;
+    const double sigw = r_in[SHAPE_REC_SIGW];
+    const float skyf = r_in[SHAPE_REC_SKY0];
+    const double c = -1.0 / (2.0 * sigw * sigw);           // W' = c W
+    const float cw = (float)(kLog2e / (2.0 * sigw * sigw));
+    double x = r_in[SHAPE_REC_X0], y = r_in[SHAPE_REC_Y0];
+    double g1 = 0.0, g2 = 0.0;
+    uint32_t stt = 0;
+    int it = 0;
+    while (it < o.max_iter_moments) {
+      // R^2 of App. A: [(1-g1)^2+g2^2] t1^2 + [(1+g1)^2+g2^2] t2^2 - 4 g2 t1 t2
+      const float a11 = (float)((1.0 - g1) * (1.0 - g1) + g2 * g2);
+      const float a22 = (float)((1.0 + g1) * (1.0 + g1) + g2 * g2);
+      const float a12 = (float)(-4.0 * g2);
+      const float xf = (float)x, yf = (float)y;
+      Mom M = {};
+      for_pixels(W, [&](int k, int i, int j) {
+        float v = load_px<DT>(b.pixels, st.off, k, st.scale);
+        float t1 = (float)j - xf, t2 = (float)i - yf;
+        float s11 = t1 * t1, s22 = t2 * t2, s12 = t1 * t2;
+        float r2 = fmaf(a11, s11, fmaf(a22, s22, a12 * s12));
+        float fw = (v - skyf) * fast_exp2(-r2 * cw);
+        M.m00 += (double)fw;
+        M.m10 += (double)(fw * t1);
+        M.m01 += (double)(fw * t2);
+        float f11 = fw * s11, f22 = fw * s22, f12 = fw * s12;
+        M.m20 += (double)f11;
+        M.m02 += (double)f22;
+        M.m11 += (double)f12;
+        M.m40 = fmaf(f11, s11, M.m40);
+        M.m31 = fmaf(f11, s12, M.m31);
+        M.m22 = fmaf(f11, s22, M.m22);
+        M.m13 = fmaf(f12, s22, M.m13);
+        M.m04 = fmaf(f22, s22, M.m04);
+      });
+      M.m00 = wave_sum(M.m00);
+      M.m10 = wave_sum(M.m10);
+      M.m01 = wave_sum(M.m01);
+      M.m20 = wave_sum(M.m20);
+      M.m11 = wave_sum(M.m11);
+      M.m02 = wave_sum(M.m02);
+      M.m40 = wave_sum(M.m40);
+      M.m31 = wave_sum(M.m31);
+      M.m22 = wave_sum(M.m22);
+      M.m13 = wave_sum(M.m13);
+      M.m04 = wave_sum(M.m04);
+      ++it;
+      if (!(M.m00 > 0.0) || !(M.m20 + M.m02 > 0.0)) {
+        stt |= SHAPE_ST_NONPOSITIVE_FLUX;
+        break;
+      }
+      const Ksb K = ksb_from_moments(M, g1, g2, c);
+      const double det = K.P11 * K.P22 - K.P12 * K.P21;
+      if (!(fabs(det) > 1e-300) || !__builtin_isfinite(det)) {
+        stt |= SHAPE_ST_SINGULAR;
+        break;
+      }
+      // eq. newg: dg = (1 - |g_w|^2) P^-1 (e_obs - e_w), e_w = 2 g_w / (1 + |g_w|^2)
+      const double gg = g1 * g1 + g2 * g2;
+      const double r1 = K.e1 - 2.0 * g1 / (1.0 + gg), r2 = K.e2 - 2.0 * g2 / (1.0 + gg);
+      double dg1 = (1.0 - gg) * (K.P22 * r1 - K.P12 * r2) / det;
+      double dg2 = (1.0 - gg) * (-K.P21 * r1 + K.P11 * r2) / det;
+      double h = 1.0;
+      bool halved = false;
+      for (int q = 0; q < 60; ++q) {
+        const double a = g1 + h * dg1, bb = g2 + h * dg2;
+        if (a * a + bb * bb <= o.gmax * o.gmax) break;
+        h *= 0.5;
+        halved = true;
+        stt |= SHAPE_ST_G_CLAMPED;
+      }
+      dg1 *= h;
+      dg2 *= h;
+      const double dx = M.m10 / (o.k_gain * M.m00), dy = M.m01 / (o.k_gain * M.m00);
+      g1 += dg1;
+      g2 += dg2;
+      x += dx;
+      y += dy;
+      if (x < 0.0 || y < 0.0 || x > W - 1 || y > W - 1) {
+        stt |= SHAPE_ST_LOST;
+        break;
+      }
+      // a step cut at the |g_w| bound is small for that reason alone: never a stop
+      if (!halved && fabs(dx) < o.tol_x && fabs(dy) < o.tol_x && fabs(dg1) < o.tol_g &&
+          fabs(dg2) < o.tol_g) {
+        stt |= SHAPE_ST_CONVERGED;
+        break;
+      }
+    }
+    if (!(stt & (SHAPE_ST_CONVERGED | SHAPE_ST_NONPOSITIVE_FLUX | SHAPE_ST_SINGULAR | SHAPE_ST_LOST)))
+      stt |= SHAPE_ST_MAX_ITER;
+    __syncthreads();  // all lanes have read the input record
+    if (lane == 0) {
+      out[SHAPE_REC_X0] = (float)x;
+      out[SHAPE_REC_Y0] = (float)y;
+      out[SHAPE_REC_E1] = (float)g1;
+      out[SHAPE_REC_E2] = (float)g2;
+      out[SHAPE_REC_SIGW] = r_in[SHAPE_REC_SIGW];
+      out[SHAPE_REC_R50] = r_in[SHAPE_REC_R50];
+      out[SHAPE_REC_SKY0] = r_in[SHAPE_REC_SKY0];
+      out[SHAPE_REC_FLUX] = r_in[SHAPE_REC_FLUX];
+      iters[s] = it;
+      status[s] = stt;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_moments(const shape_batch& b, const KOpts& o, const float* rec_in,
+                          float* rec_out, int32_t* iters, uint32_t* status, hipStream_t stream) {
+  const int64_t grid = b.n < (1ll << 30) ? b.n : (1ll << 30);
+  if (b.dtype == SHAPE_F32)
+    hipLaunchKernelGGL(moments_kernel<SHAPE_F32>, dim3((unsigned)grid), dim3(kWave), 0, stream, b,
+                       o, rec_in, rec_out, iters, status);
+  else
+    hipLaunchKernelGGL(moments_kernel<SHAPE_F16_SCALED>, dim3((unsigned)grid), dim3(kWave), 0,
+                       stream, b, o, rec_in, rec_out, iters, status);
+  return hipGetLastError();
+}
+
+}  // namespace shape

@@ -1,0 +1,115 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/shape.h declares, and rejects bad arguments before
+launching anything."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "shape.h")
+
+
+@pytest.fixture(scope="module")
+def shape():
+    import paper_1203_0571_amd as shape
+    return shape
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(shape_[a-z_0-9]+)\s*\(",
+                                 text, flags=re.M)))
+
+
+def test_header_declares_the_stage_calls():
+    names = declared_functions()
+    for f in ["shape_centroid", "shape_moments", "shape_fit_sersic", "shape_default_opts",
+              "shape_status_string", "shape_abi_version"]:
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(shape):
+    lib = C.CDLL(shape.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert shape.lib.shape_abi_version() == 1
+
+
+def test_struct_layout_matches_header(shape):
+    # offsets fixed by the header's field order on x86-64 / LP64
+    assert C.sizeof(shape.ShapeBatch) == 6 * 8 + 8 + 8 + 4 + 4
+    assert C.sizeof(shape.ShapeOpts) == 4 * 4 + 9 * 8 + 2 * 4
+
+
+def test_defaults(shape):
+    o = shape.default_opts()
+    assert o.max_iter_centroid == 20 and o.max_iter_moments == 20 and o.max_iter_lm == 30
+    assert o.k_gain == 0.75 and o.free_mask == 0xFF and o.gmax == 0.95
+    assert shape.lib.shape_default_opts(None) == shape.EINVAL
+
+
+def test_status_strings(shape):
+    for code in [0, -1, -2, -3, -4, 7]:
+        assert isinstance(shape.lib.shape_status_string(code), bytes)
+
+
+def _batch(shape, **kw):
+    b = shape.ShapeBatch()
+    b.pixels = 0x1000
+    b.sigma = 0x2000
+    b.n = 4
+    b.n_pixels = 4 * 16 * 16
+    b.side0 = 16
+    b.dtype = shape.F32
+    for k, v in kw.items():
+        setattr(b, k, v)
+    return b
+
+
+def test_argument_errors_return_einval_without_launch(shape):
+    L = shape.lib
+    o = shape.default_opts()
+    out = C.c_void_p(0x3000)
+    cases = [
+        _batch(shape, pixels=None),
+        _batch(shape, sigma=None),
+        _batch(shape, n=-1),
+        _batch(shape, side0=3),
+        _batch(shape, side0=129),
+        _batch(shape, dtype=7),
+        _batch(shape, dtype=shape.F16_SCALED),          # scale missing
+        _batch(shape, n_pixels=3 * 16 * 16),            # uniform batch overruns the buffer
+    ]
+    for b in cases:
+        assert L.shape_centroid(C.byref(b), C.byref(o), out, out, out, None) == shape.EINVAL
+        assert L.shape_moments(C.byref(b), C.byref(o), out, out, out, out, None) == shape.EINVAL
+        assert L.shape_fit_sersic(C.byref(b), C.byref(o), out, out, out, out, None, out, out,
+                                  None, None) == shape.EINVAL
+    b = _batch(shape)
+    assert L.shape_centroid(None, C.byref(o), out, out, out, None) == shape.EINVAL
+    assert L.shape_centroid(C.byref(b), None, out, out, out, None) == shape.EINVAL
+    assert L.shape_centroid(C.byref(b), C.byref(o), None, out, out, None) == shape.EINVAL
+    assert L.shape_fit_sersic(C.byref(b), C.byref(o), None, None, out, out, None, out, out,
+                              None, None) == shape.EINVAL
+    for field, val in [("k_gain", 0.0), ("gmax", 1.0), ("lambda0", -1.0), ("n0", 0.1),
+                       ("max_iter_lm", -1), ("moffat_beta", 1.0)]:
+        ob = shape.default_opts(**{field: val})
+        assert L.shape_centroid(C.byref(b), C.byref(ob), out, out, out, None) == shape.EINVAL
+
+
+def test_unsupported_mask_and_empty_batch(shape):
+    L = shape.lib
+    out = C.c_void_p(0x3000)
+    b = _batch(shape)
+    o = shape.default_opts(free_mask=0x0F)
+    assert L.shape_fit_sersic(C.byref(b), C.byref(o), out, out, out, out, None, out, out,
+                              None, None) == shape.EUNSUPPORTED
+    e = _batch(shape, n=0, pixels=None, sigma=None)
+    o = shape.default_opts()
+    assert L.shape_centroid(C.byref(e), C.byref(o), None, None, None, None) == shape.OK
+    assert L.shape_moments(C.byref(e), C.byref(o), None, None, None, None, None) == shape.OK
+    assert L.shape_fit_sersic(C.byref(e), C.byref(o), None, None, None, None, None, None, None,
+                              None, None) == shape.OK

@@ -1,0 +1,153 @@
+"""GPU parity: the HIP stages against the FP64 oracle on seeded stamps.
+
+Bars (stamps where both sides report CONVERGED): |dx|, |dy| <= 1e-3 px,
+|de| <= 1e-4, relative 1e-3 on Re and n.  Inputs are the synthetic
+workloads of the generator (the paper's simulation recipe, Sec. 4.1)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import BAR_E, BAR_REL, BAR_X, compare, oracle_opts_like, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def shape():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1203_0571_amd as shape
+    return shape
+
+
+def _check_bars(r, min_both_frac, min_ok=1.0):
+    assert r["fit_both"] >= min_both_frac * r["n"], r
+    assert r["centroid_dxy"] <= BAR_X, r
+    assert r["moments_dxy"] <= BAR_X and r["moments_de"] <= BAR_E, r
+    assert r["fit_x_ok"] >= min_ok and r["fit_e_ok"] >= min_ok and r["fit_rel_ok"] >= min_ok, r
+
+
+def test_gaussian_workload_4_params(shape):
+    """1,000 x 32^2 Gaussian galaxies, centroid + moments + (Re, n, I0, sky) fit."""
+    b = synth.make("plain32")
+    o = shape.default_opts(free_mask=shape.MASK_SIZE)
+    g = run_gpu(shape, b, o)
+    ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
+    r = compare(g, ref, 0xF0, "plain32")
+    assert r["r50_rel"] < 1e-5 and r["sigw_rel"] < 1e-5
+    assert r["status0_agree"] > 0.99 and r["status1_agree"] > 0.99
+    _check_bars(r, 0.98)
+    # the centre and ellipticity are held in the 4-parameter fit
+    conv = (g["status"][:, 2] & shape.ST_CONVERGED) != 0
+    np.testing.assert_array_equal(g["p"][conv, :4], g["moments"][conv, :4])
+
+
+@pytest.mark.parametrize("workload,count", [("plain48", 2048), ("sersic64", 1024)])
+def test_sersic_workloads_8_params(shape, workload, count):
+    b = synth.make(workload, count=count)
+    o = shape.default_opts()
+    g = run_gpu(shape, b, o)
+    ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
+    r = compare(g, ref, 0xFF, workload)
+    _check_bars(r, 0.85, min_ok=0.995)
+
+
+def test_fp16_storage(shape):
+    """FP16 stamps with a per-stamp scale: the oracle reads the same dequantised pixels."""
+    b = synth.make("sersic64h", count=1024)
+    o = shape.default_opts()
+    g = run_gpu(shape, b, o)
+    ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
+    r = compare(g, ref, 0xFF, "sersic64h")
+    _check_bars(r, 0.85, min_ok=0.995)
+
+
+def test_uneven_sizes_and_moffat_stars(shape):
+    b = synth.make("uneven", count=1024)
+    o = shape.default_opts()
+    g = run_gpu(shape, b, o)
+    ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
+    r = compare(g, ref, 0xFF, "uneven")
+    _check_bars(r, 0.8, min_ok=0.99)
+    stars = b.model == 1
+    assert ((g["status"][stars, 2] & shape.ST_CONVERGED) != 0).mean() > 0.8
+
+
+def _custom_batch(stamps, sigmas, sides=None, offsets=None, n_pixels=None):
+    pix = np.concatenate([np.asarray(s, np.float32).ravel() for s in stamps])
+    sides_a = np.array([s.shape[0] for s in stamps] if sides is None else sides, np.int32)
+    if offsets is None:
+        offsets = np.concatenate([[0], np.cumsum([s.size for s in stamps])[:-1]]).astype(np.int64)
+    b = synth.Batch("custom", pix, np.asarray(offsets, np.int64), sides_a,
+                    np.asarray(sigmas, np.float32), np.zeros(len(stamps), np.uint8),
+                    np.zeros((len(stamps), 8)), None)
+    return b
+
+
+def test_edge_cases(shape):
+    import torch
+    rng = np.random.default_rng(7)
+    small = synth.render_sersic(4, np.array([1.6, 1.4, 0.1, 0.0, 1.0, 1.0, 500.0, 10.0]))[0] + 10
+    small = small + rng.normal(0, 1.0, small.shape)
+    big = synth.render_sersic(128, np.array([63.2, 64.1, 0.3, -0.2, 9.0, 1.5, 300.0, 10.0]))[0] + 10
+    big = big + rng.normal(0, 2.0, big.shape)
+    mid = synth.render_sersic(40, np.array([19.2, 20.1, 0.2, 0.1, 3.0, 2.0, 800.0, 10.0]))[0] + 10
+    mid = mid + rng.normal(0, 3.0, mid.shape)
+    nan = mid.copy()
+    nan[5, 7] = np.nan
+    flat = np.full((24, 24), 10.0)
+    stamps = [small, big, mid, nan, mid, flat]
+    sig = [1.0, 2.0, 3.0, 3.0, -1.0, 1.0]
+    b = _custom_batch(stamps, sig)
+    g = run_gpu(shape, b)
+    ref = oracle.pipeline(b, oracle_opts_like(shape.default_opts(), tol_lm=1e-9, max_iter_lm=200))
+    st = g["status"]
+    assert st[3, 0] == shape.ST_NONFINITE_INPUT and np.isnan(g["p"][3]).all()
+    assert st[4, 0] == shape.ST_BAD_INPUT and st[4, 2] == shape.ST_BAD_INPUT
+    assert st[5, 0] & shape.ST_NONPOSITIVE_FLUX
+    np.testing.assert_array_equal(st[:, 0], ref["status"][:, 0])
+    for s in (1, 2):   # max side and an ordinary ragged stamp
+        assert st[s, 2] & shape.ST_CONVERGED and ref["status"][s, 2] & oracle.CONVERGED
+        assert np.abs(g["p"][s, :2] - ref["p"][s, :2]).max() <= BAR_X
+        assert np.abs(g["p"][s, 2:4] - ref["p"][s, 2:4]).max() <= BAR_E
+        assert np.abs(g["p"][s, 4:6] / ref["p"][s, 4:6] - 1).max() <= BAR_REL
+    # side out of range and a stamp that overruns the pixel buffer
+    b2 = _custom_batch([mid, mid, mid], [3.0, 3.0, 3.0], sides=[3, 200, 40],
+                       offsets=[0, 0, 40 * 40 * 2 + 1])
+    g2 = run_gpu(shape, b2)
+    assert (g2["status"][:, 0] == shape.ST_BAD_INPUT).all()
+    assert np.isnan(g2["p"]).all()
+    # empty batch
+    e = shape.DeviceBatch(pixels=torch.zeros(0, device="cuda"), sigma=torch.zeros(0, device="cuda"),
+                          side0=16)
+    out = shape.pipeline(e)
+    assert out["p"].shape == (0, 8)
+
+
+def test_deterministic(shape):
+    b = synth.make("plain48", count=512)
+    g1 = run_gpu(shape, b)
+    g2 = run_gpu(shape, b)
+    for k in ("centroid", "moments", "p", "chi2", "iters", "status"):
+        np.testing.assert_array_equal(g1[k], g2[k])
+
+
+def test_full_size_sampled(shape):
+    """The 65,536 x 64^2 workload at full size in one launch per stage; 128
+    sampled stamps are recomputed by the oracle one by one."""
+    b = synth.make("sersic64")
+    o = shape.default_opts()
+    g = run_gpu(shape, b, o)
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(b.n, 128, replace=False))
+    sub = synth.Batch("sample", np.concatenate([b.pixels[b.offsets[i]:b.offsets[i] + 4096] for i in idx]),
+                      np.arange(128, dtype=np.int64) * 4096, b.sides[idx], b.sigma[idx],
+                      b.model[idx], b.truth[idx], None)
+    ref = oracle.pipeline(sub, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
+    gs = {k: v[idx] for k, v in g.items() if isinstance(v, np.ndarray) and v.shape[:1] == (b.n,)}
+    r = compare(gs, ref, 0xFF, "sersic64 full, sampled")
+    _check_bars(r, 0.85, min_ok=0.99)
+    conv = (g["status"][:, 2] & shape.ST_CONVERGED) != 0
+    print("full-size convergence fraction %.4f" % conv.mean())
+    assert conv.mean() > 0.85

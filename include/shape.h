@@ -176,6 +176,79 @@ int shape_fit_sersic(const shape_batch* batch, const shape_opts* opts, const flo
                      const float* rec, float* p_out, float* chi2, float* perr,
                      int32_t* iters, uint32_t* status, int32_t* sweeps, void* stream);
 
+/*
+ * chi^2 of given parameters (Sec. 4.1, eq. chi2): chi2[i] = sum over the
+ * pixels of stamp i of ((d - m(p_i)) / sigma_i)^2, m the model above (Moffat
+ * stamps read beta from slot 5).
+ *   params [n][8] in (device), chi2 [n] out.
+ * Non-finite parameters give NaN for that stamp.
+ */
+int shape_chi2_fwd(const shape_batch* batch, const float* params, float* chi2, void* stream);
+
+/*
+ * Gradient of chi^2 by the adjoint of the render: with r = (d - m)/sigma the
+ * adjoint of a pixel is -(2/sigma) r dL/dchi2 and grad_p[i][k] =
+ * sum over pixels of that adjoint times dm/dp_k (all eight parameters).
+ *   params    [n][8] in
+ *   grad_chi2 [n] in, the upstream dL/dchi2 per stamp, or NULL for 1
+ *   chi2      [n] out or NULL
+ *   grad_p    [n][8] out
+ *   jtj       [n][36] out or NULL: J^T J / sigma^2, upper triangle row by row
+ *   jtr       [n][8] out or NULL: J^T (d - m) / sigma^2 (the LM right-hand side)
+ */
+int shape_chi2_bwd(const shape_batch* batch, const float* params, const float* grad_chi2,
+                   float* chi2, float* grad_p, float* jtj, float* jtr, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Work-queue form of shape_fit_sersic for batches of uneven stamps (any mix
+ * of sides and of Sersic / Moffat stamps).  The same LM trials as the fused
+ * fit, one trial per stamp per step:
+ *   shape_queue_start   orders the stamps largest side first (on the device)
+ *                       and computes every stamp's starting point;
+ *   shape_queue_step    one persistent launch: workgroups pop stamps from an
+ *                       atomic cursor and advance each still-active stamp by
+ *                       one LM trial (the state lives in the workspace);
+ *   shape_queue_finish  writes the same outputs as shape_fit_sersic.
+ * A step can be captured once into a hipGraph and replayed
+ * (shape_queue_graph_*).  The caller owns the workspace (device memory of
+ * shape_queue_workspace_bytes(n) bytes); its first 16 bytes are four uint32
+ * (next_big, next_small, active, n_team): `active` counts the stamps still
+ * iterating after the last step and is valid once the stream has
+ * synchronised.  Steps on one workspace must not overlap.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t team;           /* waves per stamp for stamps with side >= team_min_side: 1, 2, 4 */
+  int32_t team_min_side;  /* threshold side for team processing (team > 1) */
+  int32_t grid;           /* persistent workgroups; 0 = as many as fit on the device */
+  int32_t reserved;
+} shape_queue_cfg;
+
+/* Defaults: team 1 (one wave per stamp), grid 0. */
+int shape_queue_default_cfg(shape_queue_cfg* cfg);
+/* Workspace bytes for n stamps (about 450 B per stamp). */
+int shape_queue_workspace_bytes(int64_t n, size_t* bytes);
+/* Starting points (p_init [n][8] or, if NULL, the moments records rec [n][8]). */
+int shape_queue_start(const shape_batch* batch, const shape_opts* opts, const shape_queue_cfg* cfg,
+                      const float* p_init, const float* rec, void* ws, size_t ws_bytes,
+                      void* stream);
+/* One LM trial for every still-active stamp. */
+int shape_queue_step(const shape_batch* batch, const shape_opts* opts, const shape_queue_cfg* cfg,
+                     void* ws, size_t ws_bytes, void* stream);
+/* Outputs, as shape_fit_sersic (stamps still active are flagged MAX_ITER). */
+int shape_queue_finish(const shape_batch* batch, const shape_opts* opts, void* ws,
+                       size_t ws_bytes, float* p_out, float* chi2, float* perr, int32_t* iters,
+                       uint32_t* status, int32_t* sweeps, void* stream);
+
+/* A captured step: the batch, options, configuration and workspace are bound
+ * at creation.  The handle is host memory owned by the library until
+ * shape_queue_graph_destroy. */
+typedef struct shape_queue_graph shape_queue_graph;
+int shape_queue_graph_create(const shape_batch* batch, const shape_opts* opts,
+                             const shape_queue_cfg* cfg, void* ws, size_t ws_bytes,
+                             shape_queue_graph** graph);
+int shape_queue_graph_launch(shape_queue_graph* graph, void* stream);
+int shape_queue_graph_destroy(shape_queue_graph* graph);
+
 #ifdef __cplusplus
 }
 #endif

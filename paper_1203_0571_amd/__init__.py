@@ -16,7 +16,7 @@ from dataclasses import dataclass
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libshape.so")
+LIB_PATH = os.environ.get("SHAPE_LIB") or os.path.join(_PKG, "libshape.so")
 
 OK = 0
 EINVAL = -1
@@ -80,6 +80,15 @@ class ShapeOpts(C.Structure):
     ]
 
 
+class QueueCfg(C.Structure):
+    _fields_ = [
+        ("team", C.c_int32),
+        ("team_min_side", C.c_int32),
+        ("grid", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libshape.so is not built (run __graft_entry__.build() or "
@@ -97,6 +106,23 @@ def _load():
     lib.shape_moments.restype = C.c_int
     lib.shape_fit_sersic.argtypes = [bp, op, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.shape_fit_sersic.restype = C.c_int
+    lib.shape_chi2_fwd.argtypes = [bp, vp, vp, vp]
+    lib.shape_chi2_fwd.restype = C.c_int
+    lib.shape_chi2_bwd.argtypes = [bp, vp, vp, vp, vp, vp, vp, vp]
+    lib.shape_chi2_bwd.restype = C.c_int
+    qp = C.POINTER(QueueCfg)
+    lib.shape_queue_default_cfg.argtypes = [qp]
+    lib.shape_queue_workspace_bytes.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
+    lib.shape_queue_start.argtypes = [bp, op, qp, vp, vp, vp, C.c_size_t, vp]
+    lib.shape_queue_step.argtypes = [bp, op, qp, vp, C.c_size_t, vp]
+    lib.shape_queue_finish.argtypes = [bp, op, vp, C.c_size_t, vp, vp, vp, vp, vp, vp, vp]
+    lib.shape_queue_graph_create.argtypes = [bp, op, qp, vp, C.c_size_t, C.POINTER(C.c_void_p)]
+    lib.shape_queue_graph_launch.argtypes = [vp, vp]
+    lib.shape_queue_graph_destroy.argtypes = [vp]
+    for f in ("shape_queue_default_cfg", "shape_queue_workspace_bytes", "shape_queue_start",
+              "shape_queue_step", "shape_queue_finish", "shape_queue_graph_create",
+              "shape_queue_graph_launch", "shape_queue_graph_destroy"):
+        getattr(lib, f).restype = C.c_int
     return lib
 
 
@@ -225,6 +251,153 @@ def fit_sersic(batch: DeviceBatch, rec: torch.Tensor | None = None,
                                 _ptr(chi2), _ptr(perr), _ptr(it), _ptr(st), _ptr(sw),
                                 _stream(dev)), "shape_fit_sersic")
     return dict(p=p, chi2=chi2, perr=perr, iters=it, status=st, sweeps=sw)
+
+
+def _params(params):
+    if params.dtype != torch.float32 or not params.is_contiguous() or params.dim() != 2 \
+            or params.shape[1] != 8:
+        raise ValueError("params must be a contiguous float32 [n, 8] tensor")
+    return params
+
+
+def chi2_fwd(batch: DeviceBatch, params: torch.Tensor) -> torch.Tensor:
+    """shape_chi2_fwd: chi^2 [n] of params [n, 8]."""
+    params = _params(params)
+    n, dev = batch.n, batch.device
+    chi2 = torch.empty(n, dtype=torch.float32, device=dev)
+    b = batch.c_struct()
+    _check(lib.shape_chi2_fwd(C.byref(b), _ptr(params), _ptr(chi2), _stream(dev)),
+           "shape_chi2_fwd")
+    return chi2
+
+
+def chi2_bwd(batch: DeviceBatch, params: torch.Tensor, grad_chi2: torch.Tensor | None = None,
+             want_normal: bool = False):
+    """shape_chi2_bwd: dict(grad [n,8], chi2 [n], jtj [n,36] and jtr [n,8] if asked)."""
+    params = _params(params)
+    n, dev = batch.n, batch.device
+    if grad_chi2 is not None:
+        grad_chi2 = grad_chi2.to(torch.float32).contiguous()
+    grad = torch.empty((n, 8), dtype=torch.float32, device=dev)
+    chi2 = torch.empty(n, dtype=torch.float32, device=dev)
+    jtj = torch.empty((n, 36), dtype=torch.float32, device=dev) if want_normal else None
+    jtr = torch.empty((n, 8), dtype=torch.float32, device=dev) if want_normal else None
+    b = batch.c_struct()
+    _check(lib.shape_chi2_bwd(C.byref(b), _ptr(params), _ptr(grad_chi2), _ptr(chi2), _ptr(grad),
+                              _ptr(jtj), _ptr(jtr), _stream(dev)), "shape_chi2_bwd")
+    return dict(grad=grad, chi2=chi2, jtj=jtj, jtr=jtr)
+
+
+class SersicChi2(torch.autograd.Function):
+    """chi^2 of the model per stamp, differentiable in the parameters; the
+    backward is the library's adjoint sweep."""
+
+    @staticmethod
+    def forward(ctx, params, batch):
+        chi2 = chi2_fwd(batch, params.detach().contiguous())
+        ctx.save_for_backward(params)
+        ctx.batch = batch
+        return chi2
+
+    @staticmethod
+    def backward(ctx, grad_chi2):
+        (params,) = ctx.saved_tensors
+        out = chi2_bwd(ctx.batch, params.detach().contiguous(), grad_chi2)
+        return out["grad"], None
+
+
+def sersic_chi2(params: torch.Tensor, batch: DeviceBatch) -> torch.Tensor:
+    return SersicChi2.apply(params, batch)
+
+
+def queue_cfg(**overrides) -> QueueCfg:
+    c = QueueCfg()
+    _check(lib.shape_queue_default_cfg(C.byref(c)), "shape_queue_default_cfg")
+    for k, v in overrides.items():
+        if not hasattr(c, k):
+            raise AttributeError(k)
+        setattr(c, k, v)
+    return c
+
+
+def queue_workspace_bytes(n: int) -> int:
+    b = C.c_size_t()
+    _check(lib.shape_queue_workspace_bytes(int(n), C.byref(b)), "shape_queue_workspace_bytes")
+    return int(b.value)
+
+
+class QueueGraph:
+    """A captured queue step (one LM trial for every active stamp)."""
+
+    def __init__(self, batch, opts, cfg, ws):
+        self._b = batch.c_struct()   # kept alive: the graph holds the values
+        self._o, self._c, self._ws = opts, cfg, ws
+        h = C.c_void_p()
+        _check(lib.shape_queue_graph_create(C.byref(self._b), C.byref(opts), C.byref(cfg),
+                                            _ptr(ws), ws.numel(), C.byref(h)),
+               "shape_queue_graph_create")
+        self.handle = h
+
+    def launch(self, device):
+        _check(lib.shape_queue_graph_launch(self.handle, _stream(device)),
+               "shape_queue_graph_launch")
+
+    def close(self):
+        if self.handle:
+            _check(lib.shape_queue_graph_destroy(self.handle), "shape_queue_graph_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def queue_active(ws: torch.Tensor) -> int:
+    """Stamps still iterating after the last step (synchronises the stream)."""
+    return int(ws[8:12].view(torch.int32).item())
+
+
+def fit_queue(batch: DeviceBatch, rec: torch.Tensor | None = None,
+              p_init: torch.Tensor | None = None, opts: ShapeOpts | None = None,
+              cfg: QueueCfg | None = None, use_graph: bool = True, check_every: int = 4,
+              want_perr: bool = False):
+    """Work-queue fit: shape_queue_start, then one LM trial per step (a hipGraph
+    replay when use_graph) until every stamp is done or max_iter_lm steps, then
+    shape_queue_finish.  Returns the fit_sersic outputs plus the step count."""
+    opts = opts or default_opts()
+    cfg = cfg or queue_cfg()
+    n, dev = batch.n, batch.device
+    p, chi2, it, st, sw = _outs(n, dev, ((n, 8), torch.float32), ((n,), torch.float32),
+                                ((n,), torch.int32), ((n,), torch.int32), ((n,), torch.int32))
+    perr = torch.empty((n, 8), dtype=torch.float32, device=dev) if want_perr else None
+    if n == 0:
+        return dict(p=p, chi2=chi2, perr=perr, iters=it, status=st, sweeps=sw, steps=0)
+    nbytes = queue_workspace_bytes(n)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = batch.c_struct()
+    _check(lib.shape_queue_start(C.byref(b), C.byref(opts), C.byref(cfg), _ptr(p_init), _ptr(rec),
+                                 _ptr(ws), nbytes, _stream(dev)), "shape_queue_start")
+    graph = QueueGraph(batch, opts, cfg, ws) if use_graph else None
+    steps = 0
+    try:
+        while steps < opts.max_iter_lm:
+            if graph:
+                graph.launch(dev)
+            else:
+                _check(lib.shape_queue_step(C.byref(b), C.byref(opts), C.byref(cfg), _ptr(ws),
+                                            nbytes, _stream(dev)), "shape_queue_step")
+            steps += 1
+            if check_every and steps % check_every == 0 and queue_active(ws) == 0:
+                break
+    finally:
+        if graph:
+            graph.close()
+    _check(lib.shape_queue_finish(C.byref(b), C.byref(opts), _ptr(ws), nbytes, _ptr(p),
+                                  _ptr(chi2), _ptr(perr), _ptr(it), _ptr(st), _ptr(sw),
+                                  _stream(dev)), "shape_queue_finish")
+    return dict(p=p, chi2=chi2, perr=perr, iters=it, status=st, sweeps=sw, steps=steps)
 
 
 def pipeline(batch: DeviceBatch, opts: ShapeOpts | None = None, want_perr: bool = False):

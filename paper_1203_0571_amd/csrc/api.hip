@@ -52,6 +52,32 @@ KOpts kopts(const shape_opts* o) {
 
 int from_hip(hipError_t e) { return e == hipSuccess ? SHAPE_OK : SHAPE_EDEVICE; }
 
+int check_queue(const shape_batch* b, const shape_opts* o, const shape_queue_cfg* c,
+                const void* ws, size_t ws_bytes) {
+  int rc = check_batch(b);
+  if (rc == SHAPE_OK) rc = check_opts(o);
+  if (rc != SHAPE_OK) return rc;
+  if (!c || (c->team != 1 && c->team != 2 && c->team != 4) || c->grid < 0) return SHAPE_EINVAL;
+  if (c->team > 1 && (c->team_min_side < kMinSide || c->team_min_side > kMaxSide))
+    return SHAPE_EINVAL;
+  if (b->n > 0x7fffffffll) return SHAPE_EINVAL;
+  if (o->free_mask != 0xFFu && o->free_mask != 0xF0u) return SHAPE_EUNSUPPORTED;
+  if (o->free_mask == 0xF0u && c->team != 1) return SHAPE_EUNSUPPORTED;
+  if (!o->linear_init) return SHAPE_EUNSUPPORTED;
+  if (b->n == 0) return SHAPE_OK;
+  if (!ws) return SHAPE_EINVAL;
+  if (ws_bytes < queue_workspace_bytes(b->n)) return SHAPE_ENOMEM;
+  return SHAPE_OK;
+}
+
+QCfg qcfg(const shape_queue_cfg* c) {
+  QCfg q;
+  q.team = c->team;
+  q.team_min_side = c->team_min_side;
+  q.grid = c->grid;
+  return q;
+}
+
 }  // namespace
 
 extern "C" {
@@ -122,6 +148,113 @@ int shape_fit_sersic(const shape_batch* b, const shape_opts* o, const float* p_i
   if ((!p_init && !rec) || !p_out || !chi2 || !iters || !status) return SHAPE_EINVAL;
   return from_hip(launch_fit(*b, kopts(o), p_init, rec, p_out, chi2, perr, iters, status,
                              sweeps, (hipStream_t)stream));
+}
+
+int shape_chi2_fwd(const shape_batch* b, const float* params, float* chi2, void* stream) {
+  int rc = check_batch(b);
+  if (rc != SHAPE_OK) return rc;
+  if (b->n == 0) return SHAPE_OK;
+  if (!params || !chi2) return SHAPE_EINVAL;
+  return from_hip(launch_chi2(*b, params, nullptr, chi2, nullptr, nullptr, nullptr, false,
+                              (hipStream_t)stream));
+}
+
+int shape_chi2_bwd(const shape_batch* b, const float* params, const float* grad_chi2,
+                   float* chi2, float* grad_p, float* jtj, float* jtr, void* stream) {
+  int rc = check_batch(b);
+  if (rc != SHAPE_OK) return rc;
+  if (b->n == 0) return SHAPE_OK;
+  if (!params || !grad_p) return SHAPE_EINVAL;
+  return from_hip(
+      launch_chi2(*b, params, grad_chi2, chi2, grad_p, jtj, jtr, true, (hipStream_t)stream));
+}
+
+int shape_queue_default_cfg(shape_queue_cfg* c) {
+  if (!c) return SHAPE_EINVAL;
+  c->team = 1;
+  c->team_min_side = 96;
+  c->grid = 0;
+  c->reserved = 0;
+  return SHAPE_OK;
+}
+
+int shape_queue_workspace_bytes(int64_t n, size_t* bytes) {
+  if (n < 0 || !bytes) return SHAPE_EINVAL;
+  *bytes = queue_workspace_bytes(n);
+  return SHAPE_OK;
+}
+
+int shape_queue_start(const shape_batch* b, const shape_opts* o, const shape_queue_cfg* c,
+                      const float* p_init, const float* rec, void* ws, size_t ws_bytes,
+                      void* stream) {
+  int rc = check_queue(b, o, c, ws, ws_bytes);
+  if (rc != SHAPE_OK || b->n == 0) return rc;
+  if (!p_init && !rec) return SHAPE_EINVAL;
+  return from_hip(launch_queue_start(*b, kopts(o), ws, p_init, rec, qcfg(c), (hipStream_t)stream));
+}
+
+int shape_queue_step(const shape_batch* b, const shape_opts* o, const shape_queue_cfg* c, void* ws,
+                     size_t ws_bytes, void* stream) {
+  int rc = check_queue(b, o, c, ws, ws_bytes);
+  if (rc != SHAPE_OK || b->n == 0) return rc;
+  return from_hip(launch_queue_step(*b, kopts(o), ws, qcfg(c), (hipStream_t)stream));
+}
+
+int shape_queue_finish(const shape_batch* b, const shape_opts* o, void* ws, size_t ws_bytes,
+                       float* p_out, float* chi2, float* perr, int32_t* iters, uint32_t* status,
+                       int32_t* sweeps, void* stream) {
+  shape_queue_cfg c;
+  shape_queue_default_cfg(&c);
+  int rc = check_queue(b, o, &c, ws, ws_bytes);
+  if (rc != SHAPE_OK || b->n == 0) return rc;
+  if (!p_out || !chi2 || !iters || !status) return SHAPE_EINVAL;
+  return from_hip(launch_queue_finish(*b, kopts(o), ws, p_out, chi2, perr, iters, status, sweeps,
+                                      (hipStream_t)stream));
+}
+
+struct shape_queue_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+int shape_queue_graph_create(const shape_batch* b, const shape_opts* o, const shape_queue_cfg* c,
+                             void* ws, size_t ws_bytes, shape_queue_graph** out) {
+  if (!out) return SHAPE_EINVAL;
+  *out = nullptr;
+  int rc = check_queue(b, o, c, ws, ws_bytes);
+  if (rc != SHAPE_OK) return rc;
+  if (b->n == 0) return SHAPE_EINVAL;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return SHAPE_EDEVICE;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = launch_queue_step(*b, kopts(o), ws, qcfg(c), s);
+    e = hipStreamEndCapture(s, &g);
+    if (le != hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(s);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return SHAPE_EDEVICE;
+  }
+  *out = new shape_queue_graph{g, x};
+  return SHAPE_OK;
+}
+
+int shape_queue_graph_launch(shape_queue_graph* g, void* stream) {
+  if (!g) return SHAPE_EINVAL;
+  return from_hip(hipGraphLaunch(g->exec, (hipStream_t)stream));
+}
+
+int shape_queue_graph_destroy(shape_queue_graph* g) {
+  if (!g) return SHAPE_EINVAL;
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  delete g;
+  return SHAPE_OK;
 }
 
 }  // extern "C"

@@ -60,30 +60,64 @@ __device__ inline float load_px(const void* base, int64_t off, int k, float scal
   }
 }
 
-// Butterfly sums over the 64 lanes; every lane ends with the same bits.
-__device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+// Sums over the 64 lanes with DPP: an inclusive scan inside each row of 16
+// lanes (row_shr 1, 2, 4, 8), then row_bcast:15 and row_bcast:31 carry the row
+// totals up, so lane 63 holds the total; it is read back as a wave-uniform
+// value (every lane gets the same bits, run after run).
+namespace dpp {
+constexpr int kShr1 = 0x111, kShr2 = 0x112, kShr4 = 0x114, kShr8 = 0x118;
+constexpr int kBcast15 = 0x142, kBcast31 = 0x143;
+template <int CTRL, int ROWS>
+__device__ inline int mov(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, true);
+}
+template <int CTRL, int ROWS>
+__device__ inline float add(float v) {
+  return v + __builtin_bit_cast(float, mov<CTRL, ROWS>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL, int ROWS>
+__device__ inline double add(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = mov<CTRL, ROWS>((int)(uint32_t)u);
+  const int hi = mov<CTRL, ROWS>((int)(uint32_t)(u >> 32));
+  return v + __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+}  // namespace dpp
+
+template <class T>
+__device__ inline T wave_total(T v) {
+  v = dpp::add<dpp::kShr1, 0xf>(v);
+  v = dpp::add<dpp::kShr2, 0xf>(v);
+  v = dpp::add<dpp::kShr4, 0xf>(v);
+  v = dpp::add<dpp::kShr8, 0xf>(v);
+  v = dpp::add<dpp::kBcast15, 0xa>(v);
+  v = dpp::add<dpp::kBcast31, 0xc>(v);
   return v;
 }
+__device__ inline float wave_sum(float v) {
+  const float t = wave_total(v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, t), 63));
+}
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-  return v;
+  const uint64_t u = __builtin_bit_cast(uint64_t, wave_total(v));
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 __device__ inline bool wave_any(bool p) { return __any(p); }
 
-// Walk the pixels owned by this lane: k = lane, lane + 64, ... with (row, col).
-template <class F>
-__device__ inline void for_pixels(int side, F&& f) {
+// Walk the pixels owned by thread `tid` of a team of STRIDE threads working on
+// one stamp: k = tid, tid + STRIDE, ... with (row, col).
+template <int STRIDE = kWave, class F>
+__device__ inline void for_pixels(int side, F&& f, int tid = -1) {
   const int npix = side * side;
-  const int lane = threadIdx.x & (kWave - 1);
-  int i = lane / side;
-  int j = lane - i * side;
-  const int di = kWave / side;
-  const int dj = kWave - di * side;
+  const int t0 = tid < 0 ? (int)(threadIdx.x & (kWave - 1)) : tid;
+  int i = t0 / side;
+  int j = t0 - i * side;
+  const int di = STRIDE / side;
+  const int dj = STRIDE - di * side;
 #pragma unroll 1
-  for (int k = lane; k < npix; k += kWave) {
+  for (int k = t0; k < npix; k += STRIDE) {
     f(k, i, j);
     i += di;
     j += dj;
@@ -94,9 +128,19 @@ __device__ inline void for_pixels(int side, F&& f) {
   }
 }
 
-// Sersic b(n) and db/dn from the generated Chebyshev table (FP64).
+// Make LDS writes of one lane visible to the other lanes of its wave (no
+// cross-wave barrier: usable where the waves of a workgroup diverge).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Sersic b(n) and db/dn from the generated Chebyshev table (FP64 series; the
+// interval variable comes from the hardware log2, which is accurate to the
+// FP32 level the sweep uses b at).
 __device__ inline void sersic_bn(double n, double* b, double* db) {
-  double x = log(n);
+  double x = (double)__builtin_amdgcn_logf((float)n) * kLn2;
   double t = (x - kBnLogLo) / (kBnLogHi - kBnLogLo) * kBnIntervals;
   // clamp in floating point first (fmin/fmax drop a NaN), so k is always a
   // valid interval; outside [0.2, 10] the series is extrapolated

@@ -15,4 +15,24 @@ hipError_t launch_fit(const shape_batch& b, const KOpts& o, const float* p_init,
                       float* p_out, float* chi2, float* perr, int32_t* iters, uint32_t* status,
                       int32_t* sweeps, hipStream_t stream);
 
+// Work-queue configuration (see shape_queue_cfg in shape.h).
+struct QCfg {
+  int team;           // waves per stamp for large stamps: 1, 2 or 4
+  int team_min_side;  // stamps with side >= this are taken by a team
+  int grid;           // persistent workgroups; 0 = all that fit on the device
+};
+
+size_t queue_workspace_bytes(int64_t n);
+hipError_t launch_queue_start(const shape_batch& b, const KOpts& o, void* ws, const float* p_init,
+                              const float* rec, const QCfg& cfg, hipStream_t stream);
+hipError_t launch_queue_step(const shape_batch& b, const KOpts& o, void* ws, const QCfg& cfg,
+                             hipStream_t stream);
+hipError_t launch_queue_finish(const shape_batch& b, const KOpts& o, void* ws, float* p_out,
+                               float* chi2, float* perr, int32_t* iters, uint32_t* status,
+                               int32_t* sweeps, hipStream_t stream);
+
+hipError_t launch_chi2(const shape_batch& b, const float* params, const float* grad_chi2,
+                       float* chi2, float* grad_p, float* jtj, float* jtr, bool grad,
+                       hipStream_t stream);
+
 }  // namespace shape

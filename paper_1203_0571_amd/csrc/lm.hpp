@@ -1,0 +1,486 @@
+// Levenberg-Marquardt profile fit of one stamp, in pieces shared by the fused
+// fit kernel (start, iterate until done, finish) and the persistent work-queue
+// kernels (start; one iteration per launch with the state in HBM; finish).
+//
+// Sec. 4.1: chi^2 (eq. chi2) of the model (eq. ser; eq. mof for stars) over
+// the free parameters, the amplitudes following from dchi2/dI0 = 0.
+//
+// Each trial is one sweep that renders the model and its Jacobian at the
+// trial shape with the current amplitudes (I0, sky) and accumulates sum r^2,
+// J^T r (FP64) and J^T J (FP32), r = d - m.  The model is linear in (I0, sky)
+// and every shape derivative is proportional to I0, so the sums at the
+// amplitude optimum of the trial shape follow from the same sweep:
+//   dl = A_LL^-1 g_L,  chi2* = chi2 - g_L . dl,  s = I0* / I0,
+//   A*_NN = s^2 A_NN,  A*_NL = s A_NL,  g*_N = s (g_N - A_NL dl),  g*_L = 0.
+// The step in the free shape parameters solves (M + lambda diag M) d = g*_N,
+// M = A*_NN - A*_NL (A*_LL)^-1 A*_LN, in FP64 by Cholesky, redundantly in every
+// thread of the team from the same reduced sums (kept in LDS).
+#pragma once
+
+#include "sweep.hpp"
+
+namespace shape {
+
+constexpr uint32_t kMaskAll = 0xFFu;
+constexpr uint32_t kMaskSize = 0xF0u;
+
+// Reduced sums of one sweep, FP64:
+//   [0] = sum r^2, [1 + k] = (J^T r)_k, [9 + tri(k, l)] = (J^T J)_kl.
+constexpr int kSums = 45;
+__host__ __device__ inline constexpr int sg(int k) { return 1 + k; }
+__host__ __device__ inline constexpr int sa(int k, int l) { return 9 + tri(k, l); }
+
+// Uniform LM state of one stamp.
+struct LmState {
+  double p[8];
+  double lambda;
+  int it;
+  int nsweep;
+  uint32_t stt;
+  int done;
+};
+
+// The LDS block one team works in: the current point's and the last trial's
+// sums, the LM state and the trial point.  Keeping the state here (not in
+// registers) while a sweep runs leaves the sweep all of the register file.
+struct LmShared {
+  double sums[2][kSums];
+  LmState L;
+  double pt[8];
+  double smax;
+  double M[21];  // damped Schur complement, lower triangle row by row
+  int cur;       // which of sums[] holds the current point
+};
+
+template <int TEAM>
+__device__ __forceinline__ void team_sync();
+
+// State updates: every thread computes the same values; thread 0 stores them.
+template <int TEAM>
+__device__ __forceinline__ void store_L(LmShared& W, const LmState& L, int tid) {
+  team_sync<TEAM>();
+  if (tid == 0) W.L = L;
+  team_sync<TEAM>();
+}
+__device__ __forceinline__ LmState load_L(const LmShared& W) { return W.L; }
+
+// Cholesky solve of the N x N SPD system M x = rhs (lower triangle of M used,
+// overwritten by the factor); one reciprocal per pivot, no other divisions.
+// Returns false if M is not positive definite.
+template <int N>
+__device__ __forceinline__ bool chol_solve(double (&M)[N][N], double (&x)[N]) {
+  double inv[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double s = M[j][j];
+#pragma unroll
+    for (int l = 0; l < j; ++l) s -= M[j][l] * M[j][l];
+    if (!(s > 0.0)) return false;
+    inv[j] = 1.0 / sqrt(s);
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      double v = M[i][j];
+#pragma unroll
+      for (int l = 0; l < j; ++l) v -= M[i][l] * M[j][l];
+      M[i][j] = v * inv[j];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double v = x[i];
+#pragma unroll
+    for (int l = 0; l < i; ++l) v -= M[i][l] * x[l];
+    x[i] = v * inv[i];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    double v = x[i];
+#pragma unroll
+    for (int l = i + 1; l < N; ++l) v -= M[l][i] * x[l];
+    x[i] = v * inv[i];
+  }
+  return true;
+}
+
+// Synchronise a team of TEAM waves (a lone wave needs no barrier).
+template <int TEAM>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (TEAM == 1)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+// One sweep at trial t; the team's reduced sums are left in S (LDS, kSums
+// doubles).  xs is LDS scratch of TEAM * kSums doubles for the cross-wave
+// combination (unused for TEAM == 1).  tid = thread index within the team.
+template <int DT, int MODEL, uint32_t EM, int TEAM>
+__device__ __forceinline__ void sweep_sums(const shape_batch& b, const Stamp& st, const TrialF& t,
+                                  double* S, double* xs, int tid) {
+  Acc<EM> acc;
+  sweep<DT, MODEL, EM, kWave * TEAM>(b, st, t, acc, tid);
+  const int lane = tid & (kWave - 1);
+  double* dst = (TEAM == 1) ? S : xs + (tid / kWave) * kSums;
+  team_sync<TEAM>();  // previous readers of S / xs are done
+  reduce_store<EM>(acc, dst, lane);
+  team_sync<TEAM>();
+  if constexpr (TEAM > 1) {
+    if (tid < kSums) {
+      double v = xs[tid];
+#pragma unroll
+      for (int w = 1; w < TEAM; ++w) v += xs[w * kSums + tid];
+      S[tid] = v;
+    }
+    team_sync<TEAM>();
+  }
+  if (tid == 0) S[sa(7, 7)] = (double)st.npix;
+  team_sync<TEAM>();
+}
+
+// Solve the free amplitudes (LIN: bit 6 = I0, bit 7 = sky) from sums taken at
+// amplitudes (I0, sky) and move the sums to that optimum (thread 0 rewrites S).
+// Returns false when the amplitude block is singular; otherwise (d6, d7) are
+// the amplitude changes.
+struct AmpStep {
+  bool ok;
+  double d6, d7;
+};
+template <uint32_t EM, uint32_t LIN, int TEAM>
+__device__ __forceinline__ AmpStep profile_amplitudes(double* S, double I0, int tid) {
+  AmpStep r{true, 0.0, 0.0};
+  const double g6 = S[sg(6)], g7 = S[sg(7)];
+  if constexpr (has(LIN, 6) && has(LIN, 7)) {
+    const double a = S[sa(6, 6)], bq = S[sa(6, 7)], c = S[sa(7, 7)];
+    const double det = a * c - bq * bq;
+    if (!(det > 0.0)) return AmpStep{false, 0.0, 0.0};
+    const double idet = 1.0 / det;
+    r.d6 = (c * g6 - bq * g7) * idet;
+    r.d7 = (a * g7 - bq * g6) * idet;
+  } else if constexpr (has(LIN, 6)) {
+    if (!(S[sa(6, 6)] > 0.0)) return AmpStep{false, 0.0, 0.0};
+    r.d6 = g6 / S[sa(6, 6)];
+  } else if constexpr (has(LIN, 7)) {
+    r.d7 = g7 / S[sa(7, 7)];
+  }
+  const double d6 = r.d6, d7 = r.d7;
+  const double sc = (I0 + d6) / I0;
+  team_sync<TEAM>();
+  if (tid == 0) {  // in place: A_NL and g_N still hold the old values here
+    S[0] -= g6 * d6 + g7 * d7;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      if (!has(EM, a)) continue;
+      const double a6 = S[sa(a, 6)], a7 = S[sa(a, 7)];
+      S[sg(a)] = sc * (S[sg(a)] - a6 * d6 - a7 * d7);
+#pragma unroll
+      for (int c = a; c < 6; ++c)
+        if (has(EM, c)) S[sa(a, c)] *= sc * sc;
+      S[sa(a, 6)] = a6 * sc;
+      S[sa(a, 7)] = a7 * sc;
+    }
+    if constexpr (has(LIN, 6)) S[sg(6)] = 0.0;
+    if constexpr (has(LIN, 7)) S[sg(7)] = 0.0;
+  }
+  team_sync<TEAM>();
+  return r;
+}
+
+// Starting point: p from p_init or the moments record, the amplitude optimum
+// at that shape (Sec. 4.1) and the first sweep, whose profiled sums become the
+// current point (W.sums[W.cur]).  The state ends in W.L.
+template <int DT, int MODEL, uint32_t MASK, int TEAM>
+__device__ __forceinline__ void lm_start(const shape_batch& b, const KOpts& o, const Stamp& st,
+                                         const float* p_init, const float* rec, int64_t s,
+                                         LmShared& W, double* xs, int tid) {
+  constexpr uint32_t EM = eff_mask(MASK, MODEL);
+  constexpr uint32_t LIN = EM & 0xC0u;
+  LmState L;
+  double* p = L.p;
+  if (p_init) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p[k] = p_init[s * 8 + k];
+  } else {
+    const float* r = rec + s * SHAPE_REC_LEN;
+    p[0] = r[SHAPE_REC_X0];
+    p[1] = r[SHAPE_REC_Y0];
+    p[2] = r[SHAPE_REC_E1];
+    p[3] = r[SHAPE_REC_E2];
+    const double r50 = r[SHAPE_REC_R50];
+    if (MODEL == SHAPE_SERSIC) {
+      p[4] = r50;
+      p[5] = o.n0;
+    } else {
+      p[4] = r50 / sqrt(exp2(1.0 / o.moffat_beta) - 1.0);
+      p[5] = o.moffat_beta;
+    }
+    p[4] = fmin(fmax(p[4], 0.1), (double)st.side);
+    p[6] = 1.0;
+    p[7] = r[SHAPE_REC_SKY0];
+  }
+  if (MODEL == SHAPE_MOFFAT) p[5] = o.moffat_beta;
+  L.lambda = o.lambda0;
+  L.it = 0;
+  L.nsweep = 0;
+  L.stt = 0;
+  L.done = 0;
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) finite = finite && __builtin_isfinite(p[k]);
+  if (!finite) {
+    L.stt = SHAPE_ST_BAD_INPUT;
+    L.done = 1;
+  }
+  if (tid == 0) W.cur = 0;
+  double* C = W.sums[0];
+  // Linear start: the free amplitudes' optimum at the starting shape, from one
+  // sweep at unit amplitude / zero sky (exact: the model is linear in them).
+  if constexpr (LIN != 0u) {
+    if (!L.done) {
+      if (has(LIN, 6)) p[6] = 1.0;
+      if (has(LIN, 7)) p[7] = 0.0;
+      store_L<TEAM>(W, L, tid);
+      sweep_sums<DT, MODEL, LIN, TEAM>(b, st, make_trial(W.L.p, MODEL, o.moffat_beta), C, xs, tid);
+      L = load_L(W);
+      if (!__builtin_isfinite(C[0])) {
+        L.stt = SHAPE_ST_NONFINITE_INPUT;
+        L.done = 1;
+      } else {
+        const AmpStep a = profile_amplitudes<LIN, LIN, TEAM>(C, p[6], tid);
+        if (!a.ok) L.stt |= SHAPE_ST_SINGULAR;
+        p[6] += a.d6;
+        p[7] += a.d7;
+      }
+    }
+  }
+  if (!L.done) {
+    if (!(p[6] > 0.0)) L.stt |= SHAPE_ST_NONPOSITIVE_FLUX;
+    L.nsweep = 1;
+    store_L<TEAM>(W, L, tid);
+    sweep_sums<DT, MODEL, EM, TEAM>(b, st, make_trial(W.L.p, MODEL, o.moffat_beta), C, xs, tid);
+    L = load_L(W);
+    if (!__builtin_isfinite(C[0])) {
+      L.stt = SHAPE_ST_NONFINITE_INPUT;
+      L.done = 1;
+    }
+  }
+  store_L<TEAM>(W, L, tid);
+}
+
+// One LM trial from the current sums; the trial's sums go to the other buffer
+// and become current when the trial is accepted.  Sets W.L.done when the fit
+// has converged or stalled; the caller enforces max_iter_lm.
+template <int DT, int MODEL, uint32_t MASK, int TEAM>
+__device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o, const Stamp& st,
+                                           LmShared& W, double* xs, int tid) {
+  constexpr uint32_t EM = eff_mask(MASK, MODEL);
+  constexpr uint32_t LIN = EM & 0xC0u;
+  constexpr uint32_t NL = EM & 0x3Fu;  // free shape parameters
+  constexpr int NN = popcount(NL);
+  const int cur = W.cur;
+  // Phase 1a: the damped Schur complement of the amplitude block, one lower-
+  // triangle entry per thread:
+  //   M_ac = A_ac - A_aL (A_LL)^-1 A_Lc = A_ac - u_a A_c6 - w_a A_c7.
+  constexpr int NT = NN * (NN + 1) / 2;
+  if (tid < NT) {
+    const double* C = W.sums[cur];
+    int a = 0, c = tid;
+    while (c > a) {
+      c -= a + 1;
+      ++a;
+    }
+    const int ka = nth_bit(NL, a), kc = nth_bit(NL, c);
+    double v = C[sa(ka, kc)];
+    if constexpr (has(LIN, 6) && has(LIN, 7)) {
+      const double L00 = C[sa(6, 6)], L01 = C[sa(6, 7)], L11 = C[sa(7, 7)];
+      const double idet = 1.0 / (L00 * L11 - L01 * L01);
+      const double a6 = C[sa(ka, 6)], a7 = C[sa(ka, 7)];
+      const double u = (L11 * a6 - L01 * a7) * idet, w = (L00 * a7 - L01 * a6) * idet;
+      v -= u * C[sa(kc, 6)] + w * C[sa(kc, 7)];
+    } else if constexpr (has(LIN, 6)) {
+      v -= C[sa(ka, 6)] * C[sa(kc, 6)] / C[sa(6, 6)];
+    } else if constexpr (has(LIN, 7)) {
+      v -= C[sa(ka, 7)] * C[sa(kc, 7)] / C[sa(7, 7)];
+    }
+    if (a == c) v *= 1.0 + W.L.lambda;
+    W.M[tid] = v;
+  }
+  team_sync<TEAM>();
+  // Phase 1b: one thread solves the step and forms the trial point.
+  if (tid == 0) {
+    LmState L = W.L;
+    const double* C = W.sums[cur];
+    bool ok = true;
+    if constexpr (has(LIN, 6) && has(LIN, 7))
+      ok = C[sa(6, 6)] * C[sa(7, 7)] - C[sa(6, 7)] * C[sa(6, 7)] > 0.0;
+    else if constexpr (has(LIN, 6))
+      ok = C[sa(6, 6)] > 0.0;
+    else if constexpr (has(LIN, 7))
+      ok = C[sa(7, 7)] > 0.0;
+    double M[NN][NN], x[NN];
+#pragma unroll
+    for (int a = 0; a < NN; ++a) {
+#pragma unroll
+      for (int c = 0; c <= a; ++c) M[a][c] = W.M[a * (a + 1) / 2 + c];
+      x[a] = C[sg(nth_bit(NL, a))];
+    }
+    ++L.it;
+    bool inside = false;
+    double smax = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) W.pt[k] = L.p[k];
+    if (!ok || !chol_solve<NN>(M, x)) {
+      L.stt |= SHAPE_ST_SINGULAR;
+    } else {
+      double pt[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) pt[k] = L.p[k];
+      const double iscl[6] = {1.0, 1.0, 1.0, 1.0, 1.0 / L.p[4], 1.0 / L.p[5]};
+#pragma unroll
+      for (int a = 0; a < NN; ++a) {
+        pt[nth_bit(NL, a)] += x[a];
+        smax = fmax(smax, fabs(x[a]) * iscl[nth_bit(NL, a)]);
+      }
+      const double gmax2 = o.gmax * o.gmax;
+      inside = pt[2] * pt[2] + pt[3] * pt[3] < gmax2 && pt[4] >= 0.1 &&
+               pt[4] <= (double)st.side && pt[6] > 0.0 && __builtin_isfinite(pt[0]) &&
+               __builtin_isfinite(pt[1]) && __builtin_isfinite(pt[7]);
+      if (MODEL == SHAPE_SERSIC) inside = inside && pt[5] >= 0.2 && pt[5] <= 10.0;
+      if (!inside) L.stt |= SHAPE_ST_AT_BOUND;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) W.pt[k] = pt[k];
+    }
+    if (!inside) {  // rejected before any sweep
+      L.lambda *= 10.0;
+      if (L.lambda > 1e10) {
+        L.stt |= SHAPE_ST_STALLED;
+        L.done = 1;
+      }
+      W.smax = -1.0;  // no sweep for this trial
+    } else {
+      ++L.nsweep;
+      W.smax = smax;
+    }
+    W.L = L;
+  }
+  team_sync<TEAM>();
+  if (W.smax < 0.0) return;
+  // Phase 2: the sweep at the trial point (nothing else is live here).
+  double* T = W.sums[cur ^ 1];
+  sweep_sums<DT, MODEL, EM, TEAM>(b, st, make_trial(W.pt, MODEL, o.moffat_beta), T, xs, tid);
+  // Phase 3: amplitudes at the trial shape, then accept or reject.
+  LmState L = load_L(W);
+  double pt[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) pt[k] = W.pt[k];
+  const double smax = W.smax;
+  bool inside = true;
+  if (LIN != 0u) {
+    const AmpStep a = profile_amplitudes<EM, LIN, TEAM>(T, pt[6], tid);
+    pt[6] += a.d6;
+    pt[7] += a.d7;
+    inside = a.ok && pt[6] > 0.0 && __builtin_isfinite(pt[7]);
+  }
+  const double c2t = T[0];
+  const double c2c = W.sums[cur][0];
+  int next = cur;
+  if (!inside) {
+    L.stt |= SHAPE_ST_AT_BOUND;
+    L.lambda *= 10.0;
+    if (L.lambda > 1e10) {
+      L.stt |= SHAPE_ST_STALLED;
+      L.done = 1;
+    }
+  } else if (__builtin_isfinite(c2t) && c2t <= c2c * (1.0 + o.chi2_rtol)) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) L.p[k] = pt[k];
+    next = cur ^ 1;
+    L.lambda = fmax(L.lambda * 0.1, 1e-9);
+    if (smax < o.tol_lm) {
+      L.stt |= SHAPE_ST_CONVERGED;
+      L.done = 1;
+    }
+  } else {
+    L.lambda *= 10.0;
+    if (L.lambda > 1e10) {
+      L.stt |= SHAPE_ST_STALLED;
+      L.done = 1;
+    }
+  }
+  team_sync<TEAM>();
+  if (tid == 0) {
+    W.L = L;
+    W.cur = next;
+  }
+  team_sync<TEAM>();
+}
+
+// Outputs of a finished (or capped) fit from its state and current sums C:
+// parameters, chi^2, optional sqrt(diag((J^T J / sigma^2)^-1)) over the fitted
+// parameters, iterations, status, sweeps.
+template <int MODEL, uint32_t MASK>
+__device__ __forceinline__ void lm_finish(const KOpts& o, const Stamp& st, LmState L,
+                                          const double* C, int64_t s, float* p_out,
+                                          float* chi2_out, float* perr, int32_t* iters,
+                                          uint32_t* status, int32_t* sweeps, int tid) {
+  constexpr uint32_t EM = eff_mask(MASK, MODEL);
+  constexpr uint32_t LIN = EM & 0xC0u;
+  constexpr uint32_t NL = EM & 0x3Fu;
+  const bool valid = !(L.stt & (SHAPE_ST_BAD_INPUT | SHAPE_ST_NONFINITE_INPUT));
+  if (valid && !(L.stt & (SHAPE_ST_CONVERGED | SHAPE_ST_STALLED))) L.stt |= SHAPE_ST_MAX_ITER;
+  if (tid == 0) {
+    if (perr) {
+      // sigma_p = sigma sqrt(diag(A^-1)) over the fitted parameters, A = J^T J:
+      // A = L L^T by Cholesky, then diag(A^-1)_c = sum_i (L^-1)_ic^2.
+      constexpr uint32_t FM = NL | LIN;
+      constexpr int NF = popcount(FM);
+      double Lf[NF][NF], Li[NF][NF];
+      bool okf = valid;
+#pragma unroll
+      for (int j = 0; j < NF; ++j) {
+        double sjj = C[sa(nth_bit(FM, j), nth_bit(FM, j))];
+#pragma unroll
+        for (int l = 0; l < j; ++l) sjj -= Lf[j][l] * Lf[j][l];
+        okf = okf && sjj > 0.0;
+        const double d = sqrt(fmax(sjj, 1e-300));
+        Lf[j][j] = d;
+        Li[j][j] = 1.0 / d;
+#pragma unroll
+        for (int i = j + 1; i < NF; ++i) {
+          double v = C[sa(nth_bit(FM, i), nth_bit(FM, j))];
+#pragma unroll
+          for (int l = 0; l < j; ++l) v -= Lf[i][l] * Lf[j][l];
+          Lf[i][j] = v * Li[j][j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+#pragma unroll
+        for (int i = j + 1; i < NF; ++i) {
+          double v = 0.0;
+#pragma unroll
+          for (int k = j; k < i; ++k) v += Lf[i][k] * Li[k][j];
+          Li[i][j] = -v * Li[i][i];
+        }
+      double e[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) e[k] = valid ? 0.0 : (double)qnan();
+#pragma unroll
+      for (int c = 0; c < NF; ++c) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int i = c; i < NF; ++i) d2 += Li[i][c] * Li[i][c];
+        e[nth_bit(FM, c)] = okf ? st.sigma * sqrt(d2) : (double)qnan();
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) perr[s * 8 + k] = (float)e[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p_out[s * 8 + k] = valid ? (float)L.p[k] : qnan();
+    chi2_out[s] = valid ? (float)(C[0] / (st.sigma * st.sigma)) : qnan();
+    iters[s] = L.it;
+    status[s] = L.stt;
+    if (sweeps) sweeps[s] = L.nsweep;
+  }
+}
+
+}  // namespace shape

@@ -44,6 +44,7 @@ from __future__ import annotations
 
 import math
 import os
+import sys
 from concurrent.futures import ProcessPoolExecutor
 from dataclasses import dataclass, field
 
@@ -277,6 +278,14 @@ class Batch:
             a = a * float(self.scale[i])
         return a
 
+    def head(self, m):
+        """The first m stamps as a Batch of their own (same storage)."""
+        m = min(int(m), self.n)
+        end = int(self.offsets[m - 1] + int(self.sides[m - 1]) ** 2) if m else 0
+        return Batch(self.workload, self.pixels[:end], self.offsets[:m].copy(), self.sides[:m],
+                     self.sigma[:m], self.model[:m], self.truth[:m],
+                     None if self.scale is None else self.scale[:m], self.start, dict(self.meta))
+
     def dequantised_f64(self):
         """All pixels as FP64 (FP16 storage multiplied by its exact scale)."""
         if self.scale is None:
@@ -309,6 +318,10 @@ def make(workload, count=None, start=0, seed=0, storage=None, workers=None):
         c += 1
     if workers is None:
         workers = min(len(jobs), int(os.environ.get("SYNTH_WORKERS", min(16, os.cpu_count() or 1))))
+        # never fork workers from a process whose GPU runtime is already up
+        tmod = sys.modules.get("torch")
+        if tmod is not None and tmod.cuda.is_initialized():
+            workers = 1
     if workers > 1 and len(jobs) > 1:
         with ProcessPoolExecutor(max_workers=workers) as ex:
             chunks = list(ex.map(_make_chunk, jobs))

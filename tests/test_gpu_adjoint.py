@@ -1,0 +1,125 @@
+"""GPU: chi^2 forward and its adjoint gradient (shape_chi2_fwd / _bwd and the
+torch.autograd.Function) against the FP64 oracle's analytic gradient and FP64
+central finite differences (step 1e-5 relative)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def shape():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1203_0571_amd as shape
+    return shape
+
+
+def _params_away_from_optimum(b):
+    """Truth perturbed deterministically (the gradient is checked off the minimum)."""
+    rng = np.random.default_rng(42)
+    p = b.truth.copy()
+    p[:, 0:2] += rng.uniform(-0.3, 0.3, (b.n, 2))
+    p[:, 2:4] *= rng.uniform(0.8, 1.2, (b.n, 2))
+    p[:, 4] *= rng.uniform(0.85, 1.15, b.n)
+    p[:, 6] *= rng.uniform(0.9, 1.1, b.n)
+    p[:, 7] += rng.uniform(-0.5, 0.5, b.n)
+    stars = b.model == 1
+    p[~stars, 5] *= rng.uniform(0.85, 1.15, (~stars).sum())
+    p[stars, 5] = 3.3     # beta away from the generating value
+    return p.astype(np.float32).astype(np.float64)
+
+
+def _scales(p, sigma):
+    """s_k: 1 px for the centre, 1 for e, and the parameter itself for Re, n, I0,
+    sigma for the sky; g_k s_k is the gradient per relative parameter change."""
+    return np.stack([np.ones(len(p)), np.ones(len(p)), np.ones(len(p)), np.ones(len(p)),
+                     p[:, 4], p[:, 5], np.abs(p[:, 6]), sigma], 1)
+
+
+def _check_grad(g_gpu, g_ref, p, sigma, rtol=1e-4):
+    """In scale-free units u_k = g_k s_k: |du_k| <= rtol * max(|u_k|, 1e-3 max_j |u_j|)."""
+    s = _scales(p, np.asarray(sigma, np.float64))
+    u_gpu, u_ref = g_gpu * s, g_ref * s
+    floor = 1e-3 * np.abs(u_ref).max(1, keepdims=True)
+    err = np.abs(u_gpu - u_ref) / np.maximum(np.abs(u_ref), floor)
+    return float(err.max())
+
+
+@pytest.mark.parametrize("workload,count", [("sersic64", 256), ("uneven", 256), ("sersic64h", 128)])
+def test_chi2_and_gradient_vs_oracle(shape, workload, count):
+    import torch
+    b = synth.make(workload, count=count)
+    db = shape.DeviceBatch.from_host(b, "cuda:0")
+    p = _params_away_from_optimum(b)
+    pt = torch.from_numpy(p.astype(np.float32)).cuda()
+    out = shape.chi2_bwd(db, pt, want_normal=True)
+    c2f = shape.chi2_fwd(db, pt)
+    torch.cuda.synchronize()
+    g_gpu = out["grad"].cpu().numpy().astype(np.float64)
+    jtj_gpu = out["jtj"].cpu().numpy().astype(np.float64)
+    c2_gpu = out["chi2"].cpu().numpy()
+    np.testing.assert_array_equal(c2_gpu, c2f.cpu().numpy())
+    pix = b.dequantised_f64()
+    c2_ref = np.zeros(b.n)
+    g_ref = np.zeros((b.n, 8))
+    jtj_ref = np.zeros((b.n, 36))
+    for s in range(b.n):
+        o, side = int(b.offsets[s]), int(b.sides[s])
+        img = pix[o:o + side * side].reshape(side, side)
+        c2_ref[s], g_ref[s], jtj_ref[s] = oracle.chi2(img, float(b.sigma[s]), p[s], kind=int(b.model[s]),
+                                                      want_grad=True)
+    assert np.abs(c2_gpu / c2_ref - 1).max() < 2e-5
+    err = _check_grad(g_gpu, g_ref, p, b.sigma)
+    print(workload, "max scaled gradient error vs oracle %.2e" % err)
+    assert err < 1e-4
+    rel = np.abs(jtj_gpu - jtj_ref) / np.maximum(np.abs(jtj_ref), 1e-6 * np.abs(jtj_ref).max(1, keepdims=True))
+    assert rel.max() < 1e-4
+
+
+def test_gradient_vs_finite_differences(shape):
+    import torch
+    b = synth.make("sersic64", count=32)
+    db = shape.DeviceBatch.from_host(b, "cuda:0")
+    p = _params_away_from_optimum(b)
+    pt = torch.from_numpy(p.astype(np.float32)).cuda()
+    g_gpu = shape.chi2_bwd(db, pt)["grad"].cpu().numpy().astype(np.float64)
+    g_fd = np.zeros_like(g_gpu)
+    for s in range(b.n):
+        img = b.stamp(s)
+        sg = float(b.sigma[s])
+        scl = np.array([1, 1, 1, 1, p[s, 4], p[s, 5], abs(p[s, 6]), sg])
+        for k in range(8):
+            h = 1e-5 * max(abs(p[s, k]), scl[k])
+            d = np.zeros(8)
+            d[k] = h
+            g_fd[s, k] = (oracle.chi2(img, sg, p[s] + d) - oracle.chi2(img, sg, p[s] - d)) / (2 * h)
+    err = _check_grad(g_gpu, g_fd, p, b.sigma)
+    print("max scaled gradient error vs FP64 central differences %.2e" % err)
+    assert err < 1e-4
+
+
+def test_autograd_function(shape):
+    import torch
+    b = synth.make("sersic64", count=64)
+    db = shape.DeviceBatch.from_host(b, "cuda:0")
+    p = torch.from_numpy(_params_away_from_optimum(b).astype(np.float32)).cuda().requires_grad_(True)
+    w = torch.linspace(0.5, 1.5, b.n, device="cuda")
+    loss = (shape.sersic_chi2(p, db) * w).sum()
+    (grad,) = torch.autograd.grad(loss, p)
+    direct = shape.chi2_bwd(db, p.detach(), w)["grad"]
+    torch.testing.assert_close(grad, direct, rtol=0, atol=0)
+
+
+def test_bad_parameters_give_nan(shape):
+    import torch
+    b = synth.make("sersic64", count=4)
+    db = shape.DeviceBatch.from_host(b, "cuda:0")
+    p = torch.from_numpy(b.truth.astype(np.float32)).cuda()
+    p[1, 4] = float("nan")
+    out = shape.chi2_bwd(db, p)
+    assert torch.isnan(out["chi2"][1]) and torch.isnan(out["grad"][1]).all()
+    assert torch.isfinite(out["chi2"][[0, 2, 3]]).all()

@@ -1,0 +1,100 @@
+"""GPU: the work-queue form of the fit (persistent launch per LM trial,
+hipGraph replays, teams of waves for large stamps) against the fused fit and
+the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import compare, oracle_opts_like
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def shape():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1203_0571_amd as shape
+    return shape
+
+
+def _moments(shape, db, o):
+    rec0, _, _ = shape.centroid(db, o)
+    rec1, _, _ = shape.moments(db, rec0, o)
+    return rec1
+
+
+def _np(d):
+    return {k: v.cpu().numpy() for k, v in d.items() if hasattr(v, "cpu")}
+
+
+def test_queue_equals_fused_fit(shape):
+    """One wave per stamp: the queue runs the fused kernel's LM trials one per
+    step, so the results are bit-identical."""
+    import torch
+    b = synth.make("sersic64", count=512)
+    db = shape.DeviceBatch.from_host(b, "cuda:0")
+    o = shape.default_opts()
+    rec = _moments(shape, db, o)
+    fused = _np(shape.fit_sersic(db, rec=rec, opts=o, want_perr=True))
+    for use_graph in (False, True):
+        q = shape.fit_queue(db, rec=rec, opts=o, cfg=shape.queue_cfg(team=1),
+                            use_graph=use_graph, want_perr=True)
+        torch.cuda.synchronize()
+        qn = _np(q)
+        for k in ("p", "chi2", "perr", "iters", "status", "sweeps"):
+            np.testing.assert_array_equal(qn[k], fused[k], err_msg=k)
+        assert 1 <= q["steps"] <= o.max_iter_lm
+
+
+def test_graph_replays_match_eager_steps(shape):
+    """Replays of the captured step, with eager work and synchronisations in
+    between, reproduce the eager steps exactly."""
+    import torch
+    b = synth.make("uneven", count=256)
+    db = shape.DeviceBatch.from_host(b, "cuda:0")
+    o = shape.default_opts(max_iter_lm=6)
+    rec = _moments(shape, db, o)
+    cfg = shape.queue_cfg(team=2, team_min_side=64)
+    a = _np(shape.fit_queue(db, rec=rec, opts=o, cfg=cfg, use_graph=False, check_every=0))
+    for _ in range(2):
+        _ = torch.ones(1000, device="cuda").sum().item()       # eager work in between
+        g = _np(shape.fit_queue(db, rec=rec, opts=o, cfg=cfg, use_graph=True, check_every=1))
+        for k in ("p", "chi2", "iters", "status"):
+            np.testing.assert_array_equal(g[k], a[k], err_msg=k)
+
+
+@pytest.mark.parametrize("team,min_side", [(1, 96), (2, 64), (4, 96)])
+def test_queue_uneven_parity(shape, team, min_side):
+    b = synth.make("uneven", count=1024)
+    db = shape.DeviceBatch.from_host(b, "cuda:0")
+    o = shape.default_opts()
+    rec = _moments(shape, db, o)
+    q = shape.fit_queue(db, rec=rec, opts=o, cfg=shape.queue_cfg(team=team, team_min_side=min_side))
+    import torch
+    torch.cuda.synchronize()
+    g = _np(q)
+    g["centroid"] = _np({"c": shape.centroid(db, o)[0]})["c"]
+    g["moments"] = rec.cpu().numpy()
+    g["status"] = np.stack([shape.centroid(db, o)[2].cpu().numpy(), shape.moments(db, shape.centroid(db, o)[0], o)[2].cpu().numpy(), g["status"]], 1)
+    ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
+    r = compare(g, ref, 0xFF, "queue team=%d" % team)
+    assert r["fit_both"] >= 0.8 * r["n"]
+    assert r["fit_x_ok"] >= 0.99 and r["fit_e_ok"] >= 0.99 and r["fit_rel_ok"] >= 0.99
+
+
+def test_queue_caps_and_empty(shape):
+    import torch
+    b = synth.make("plain48", count=64)
+    db = shape.DeviceBatch.from_host(b, "cuda:0")
+    for cap in (0, 1):
+        o = shape.default_opts(max_iter_lm=cap)
+        rec = _moments(shape, db, o)
+        q = _np(shape.fit_queue(db, rec=rec, opts=o))
+        f = _np(shape.fit_sersic(db, rec=rec, opts=o))
+        np.testing.assert_array_equal(q["p"], f["p"])
+        np.testing.assert_array_equal(q["status"], f["status"])
+    e = shape.DeviceBatch(pixels=torch.zeros(0, device="cuda"), sigma=torch.zeros(0, device="cuda"),
+                          side0=16)
+    assert shape.fit_queue(e)["p"].shape == (0, 8)

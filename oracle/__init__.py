@@ -77,6 +77,9 @@ def lib():
         L.orc_chi2.argtypes = [d, C.c_int, C.c_double, d, C.c_int, d, d]
         L.orc_fit.argtypes = [d, C.c_int, C.c_double, C.c_int, d, C.POINTER(Opts), d, d,
                               C.POINTER(C.c_int), C.POINTER(C.c_uint32), d]
+        L.orc_star_moments.argtypes = [d, C.c_int, C.c_double, C.c_double, C.c_double, d,
+                                       C.c_int, C.c_double, C.c_double, C.c_int, d,
+                                       C.POINTER(C.c_int), C.POINTER(C.c_uint32)]
         L.orc_pipeline.restype = C.c_int
         L.orc_pipeline.argtypes = [C.c_int64, d, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(Opts), d, d, d, d, C.c_void_p, C.c_void_p, C.c_int]
@@ -190,6 +193,19 @@ def fit(img, sigma, p_init, kind=SERSIC, o=None):
     lib().orc_fit(_dp(img), img.shape[0], float(sigma), kind, _dp(p0), C.byref(o), _dp(out),
                   C.byref(c2), C.byref(it), C.byref(st), _dp(perr))
     return dict(p=out, chi2=c2.value, iters=it.value, status=st.value, perr=perr)
+
+
+def star_moments(img, sky, xc, yc, g, kind, w0, tol=1e-4, max_iter=20):
+    """Sec. 4.2 star estimators; kind SERSIC = Gaussian star, MOFFAT = Moffat."""
+    img = _f64(img)
+    gg = _f64(g)
+    out = np.zeros(6)
+    it, st = C.c_int(), C.c_uint32(0)
+    lib().orc_star_moments(_dp(img), img.shape[0], float(sky), float(xc), float(yc), _dp(gg),
+                           int(kind), float(w0), float(tol), int(max_iter), _dp(out),
+                           C.byref(it), C.byref(st))
+    return dict(size=out[0], beta=out[1], I0=out[2], r0=out[3], r2=out[4], r4=out[5],
+                iters=it.value, status=st.value)
 
 
 def pipeline(batch, o=None, threads=0, pixels_f64=None):

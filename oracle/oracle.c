@@ -20,6 +20,7 @@
 #endif
 
 #define R2_MIN 1e-8   /* floor on R^2 (px^2): keeps the Sersic cusp finite */
+#define ORC_PI 3.14159265358979323846
 
 void orc_default_opts(orc_opts* o) {
   o->max_iter_centroid = 20;   /* Sec. 4.1: at most 20 iterations */
@@ -677,6 +678,82 @@ void orc_fit(const double* img, int side, double sigma, int kind, const double* 
   }
   memcpy(p_out, p, sizeof p);
   *chi2_out = chi2;
+  *iters = it;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Star shapes from weighted moments (Sec. 4.2).  About the centre (xc, yc)  */
+/* and with the ellipticity g from Secs. 2-3, r is the elliptical radius of */
+/* the model (R^2 = |S(g) theta|^2 / (1 - |g|^2)), f = I - sky, and the      */
+/* radial integrals become pixel sums:                                     */
+/*   r0 = sum f W,  r2 = sum f W R^2,  r4 = sum f W R^4.                   */
+/* Gaussian (Sec. 4.2.1, eqs. gaur0, gaur2): W = exp(-R^2 / 2 sigma_w^2);   */
+/* with sigma_w = sigma, r0 = pi sigma^2 I0 and r2 = pi sigma^4 I0, so      */
+/* sigma = sqrt(r2 / r0) and I0 = r0 / (pi sigma^2) (eqs. gausigiter,       */
+/* gauI0iter); sigma_w is then set to sigma and the moments recomputed      */
+/* until the fractional change of sigma is below tol or after max_iter.     */
+/* Moffat (Sec. 4.2.2): W = (1 + R^2 / rdw^2)^-3; with rdw = rd the moments */
+/* give beta = 1 / (r4 r0 / (2 r2^2) - 1), rd = sqrt(r2 / r0 (beta + 1)),   */
+/* I0 = r0 (beta + 2) / (pi rd^2) (eqs. mofbetaiter, mofrditer, mofI0iter); */
+/* rdw is iterated to rd the same way.                                       */
+/* out: [0] sigma or rd, [1] beta (Moffat; 0 for Gaussian), [2] I0,          */
+/*      [3] r0, [4] r2, [5] r4 of the last evaluation.                       */
+/* ------------------------------------------------------------------------ */
+static void star_sums(const double* img, int side, double sky, double xc, double yc,
+                      const double* g, int kind, double w, double* r0, double* r2, double* r4) {
+  double g1 = g[0], g2 = g[1], D = 1.0 - g1 * g1 - g2 * g2;
+  double s0 = 0, s2 = 0, s4 = 0;
+  for (int i = 0; i < side; ++i) {
+    for (int j = 0; j < side; ++j) {
+      double t1 = j - xc, t2 = i - yc;
+      double v1 = (1.0 - g1) * t1 - g2 * t2, v2 = -g2 * t1 + (1.0 + g1) * t2;
+      double R2 = (v1 * v1 + v2 * v2) / D;
+      double W = kind == ORC_SERSIC ? exp(-R2 / (2.0 * w * w)) : pow(1.0 + R2 / (w * w), -3.0);
+      double f = img[i * side + j] - sky;
+      s0 += f * W;
+      s2 += f * W * R2;
+      s4 += f * W * R2 * R2;
+    }
+  }
+  *r0 = s0;
+  *r2 = s2;
+  *r4 = s4;
+}
+
+void orc_star_moments(const double* img, int side, double sky, double xc, double yc,
+                      const double* g, int kind, double w0, double tol, int max_iter,
+                      double* out, int* iters, uint32_t* status) {
+  /* kind: ORC_SERSIC selects the Gaussian star (n = 0.5), ORC_MOFFAT the Moffat */
+  double w = w0, r0 = 0, r2 = 0, r4 = 0, size = w0, beta = 0.0, I0 = 0.0;
+  int it = 0;
+  *status = 0;
+  while (it < max_iter) {
+    star_sums(img, side, sky, xc, yc, g, kind, w, &r0, &r2, &r4);
+    ++it;
+    if (!(r0 > 0.0) || !(r2 > 0.0)) { *status |= ORC_NONPOSITIVE_FLUX; break; }
+    double nsize;
+    if (kind == ORC_SERSIC) {
+      nsize = sqrt(r2 / r0);
+      I0 = r0 / (ORC_PI * nsize * nsize);
+    } else {
+      double q = r4 * r0 / (2.0 * r2 * r2) - 1.0;
+      if (!(q > 0.0)) { *status |= ORC_SINGULAR; break; }
+      beta = 1.0 / q;
+      nsize = sqrt(r2 / r0 * (beta + 1.0));
+      I0 = r0 * (beta + 2.0) / (ORC_PI * nsize * nsize);
+    }
+    double change = fabs(nsize - w) / nsize;
+    size = nsize;
+    w = nsize;
+    if (change < tol) { *status |= ORC_CONVERGED; break; }
+  }
+  if (!(*status & (ORC_CONVERGED | ORC_NONPOSITIVE_FLUX | ORC_SINGULAR))) *status |= ORC_MAX_ITER;
+  out[0] = size;
+  out[1] = beta;
+  out[2] = I0;
+  out[3] = r0;
+  out[4] = r2;
+  out[5] = r4;
   *iters = it;
 }
 

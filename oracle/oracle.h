@@ -99,6 +99,13 @@ void orc_fit(const double* img, int side, double sigma, int kind, const double* 
              const orc_opts* o, double* p_out, double* chi2, int* iters,
              uint32_t* status, double* perr);
 
+/* Star size from weighted moments (Sec. 4.2): kind ORC_SERSIC = Gaussian star,
+ * ORC_MOFFAT = Moffat star; w0 = starting weight width; out[6] =
+ * (sigma or rd, beta, I0, r0, r2, r4). */
+void orc_star_moments(const double* img, int side, double sky, double xc, double yc,
+                      const double* g, int kind, double w0, double tol, int max_iter,
+                      double* out, int* iters, uint32_t* status);
+
 /* Whole pipeline over a batch, OpenMP over stamps.  Returns threads used.
  * pixels: FP64 packed stamps; offsets/sides/sigma/model per stamp.
  * Outputs per stamp: xy[2] (centroid), mom[6], p[8], chi2, iters[3], status[3]. */

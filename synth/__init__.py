@@ -80,6 +80,8 @@ WORKLOADS = {
                          description="65,536 x 64x64 FP32 Sersic galaxies"),
     "sersic64h": Workload("sersic64h", 262_144, 64, "sersic", storage="f16",
                           description="262,144 x 64x64 Sersic galaxies, FP16 + per-stamp scale"),
+    "stars32": Workload("stars32", 1_000, 32, "moffat",
+                        description="1,000 x 32x32 FP32 Moffat stars, beta U(2.5,5), FWHM U(2,5)"),
 }
 
 
@@ -243,12 +245,37 @@ def _uneven_chunk(rng, k, storage):
                  star.astype(np.uint8), p, scales if storage == "f16" else None)
 
 
+def _moffat_chunk(rng, k, side, storage):
+    c = (side - 1) / 2.0
+    p = np.zeros((k, 8))
+    p[:, 0] = c + rng.uniform(-2.0, 2.0, k)
+    p[:, 1] = c + rng.uniform(-2.0, 2.0, k)
+    rad = 0.1 * np.sqrt(rng.uniform(0.0, 1.0, k))
+    phi = rng.uniform(0.0, 2.0 * math.pi, k)
+    p[:, 2] = rad * np.cos(phi)
+    p[:, 3] = rad * np.sin(phi)
+    beta = rng.uniform(2.5, 5.0, k)
+    fwhm = rng.uniform(2.0, 5.0, k)
+    p[:, 4] = fwhm / (2.0 * np.sqrt(2.0 ** (1.0 / beta) - 1.0))
+    p[:, 5] = beta
+    flux = _loguniform(rng, 1e4, 1e6, k)
+    snr = _loguniform(rng, 50.0, 500.0, k)
+    p[:, 6] = flux / moffat_flux_factor(p[:, 4], beta)
+    p[:, 7] = SKY
+    clean = render_moffat(side, p)
+    sigma = (np.sqrt((clean.reshape(k, -1) ** 2).sum(axis=1)) / snr).astype(np.float32)
+    pix, scale = _noise_and_pack(rng, side, clean, sigma.astype(np.float64), storage)
+    return Chunk(pix, np.full(k, side, np.int32), sigma, np.ones(k, np.uint8), p, scale)
+
+
 def _make_chunk(args):
     wl_name, seed, cidx, k, storage = args
     wl = WORKLOADS[wl_name]
     rng = np.random.default_rng([seed, cidx])
     if wl.kind == "uneven":
         return _uneven_chunk(rng, k, storage)
+    if wl.kind == "moffat":
+        return _moffat_chunk(rng, k, wl.side, storage)
     return _sersic_chunk(rng, k, wl.side, storage, wl.kind == "gauss32")
 
 

@@ -199,6 +199,26 @@ int shape_chi2_fwd(const shape_batch* batch, const float* params, float* chi2, v
 int shape_chi2_bwd(const shape_batch* batch, const float* params, const float* grad_chi2,
                    float* chi2, float* grad_p, float* jtj, float* jtr, void* stream);
 
+/*
+ * Star sizes from weighted moments (Sec. 4.2).  About the centre and
+ * ellipticity in rec (from shape_moments), with R the elliptical radius of
+ * the model and f = I - sky0, each step forms r0 = sum f W, r2 = sum f W R^2,
+ * r4 = sum f W R^4 for the current weight width w and then
+ *   profile 0, Gaussian star, W = exp(-R^2/2w^2): sigma = sqrt(r2/r0),
+ *            I0 = r0/(pi sigma^2)  (Sec. 4.2.1);
+ *   profile 1, Moffat star, W = (1 + R^2/w^2)^-3: beta = 1/(r4 r0/(2 r2^2) - 1),
+ *            rd = sqrt(r2/r0 (beta + 1)), I0 = r0 (beta + 2)/(pi rd^2)  (Sec. 4.2.2);
+ * sets w to the new size and repeats until the fractional change of the size
+ * is below tol (the paper: 1e-4) or after max_iter steps (the paper: 20).
+ * The weight starts at sigma_w of rec (Gaussian) or r50/sqrt(sqrt(2) - 1), the
+ * beta = 3 Moffat with the record's r50 (Moffat).
+ *   out [n][4] out: sigma or rd, beta (0 for Gaussian), I0, r0 of the last step
+ *   iters, status [n] out.
+ */
+int shape_star_moments(const shape_batch* batch, int32_t profile, const float* rec, double tol,
+                       int32_t max_iter, float* out, int32_t* iters, uint32_t* status,
+                       void* stream);
+
 /* ------------------------------------------------------------------------
  * Work-queue form of shape_fit_sersic for batches of uneven stamps (any mix
  * of sides and of Sersic / Moffat stamps).  The same LM trials as the fused

@@ -110,6 +110,8 @@ def _load():
     lib.shape_chi2_fwd.restype = C.c_int
     lib.shape_chi2_bwd.argtypes = [bp, vp, vp, vp, vp, vp, vp, vp]
     lib.shape_chi2_bwd.restype = C.c_int
+    lib.shape_star_moments.argtypes = [bp, C.c_int32, vp, C.c_double, C.c_int32, vp, vp, vp, vp]
+    lib.shape_star_moments.restype = C.c_int
     qp = C.POINTER(QueueCfg)
     lib.shape_queue_default_cfg.argtypes = [qp]
     lib.shape_queue_workspace_bytes.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
@@ -308,6 +310,22 @@ class SersicChi2(torch.autograd.Function):
 
 def sersic_chi2(params: torch.Tensor, batch: DeviceBatch) -> torch.Tensor:
     return SersicChi2.apply(params, batch)
+
+
+STAR_GAUSSIAN = 0
+STAR_MOFFAT = 1
+
+
+def star_moments(batch: DeviceBatch, rec: torch.Tensor, profile: int = STAR_GAUSSIAN,
+                 tol: float = 1e-4, max_iter: int = 20):
+    """shape_star_moments: returns (out [n,4] = size, beta, I0, r0; iters; status)."""
+    n, dev = batch.n, batch.device
+    out, it, st = _outs(n, dev, ((n, 4), torch.float32), ((n,), torch.int32), ((n,), torch.int32))
+    b = batch.c_struct()
+    _check(lib.shape_star_moments(C.byref(b), int(profile), _ptr(rec), float(tol), int(max_iter),
+                                  _ptr(out), _ptr(it), _ptr(st), _stream(dev)),
+           "shape_star_moments")
+    return out, it, st
 
 
 def queue_cfg(**overrides) -> QueueCfg:

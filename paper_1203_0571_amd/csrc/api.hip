@@ -169,6 +169,18 @@ int shape_chi2_bwd(const shape_batch* b, const float* params, const float* grad_
       launch_chi2(*b, params, grad_chi2, chi2, grad_p, jtj, jtr, true, (hipStream_t)stream));
 }
 
+int shape_star_moments(const shape_batch* b, int32_t profile, const float* rec, double tol,
+                       int32_t max_iter, float* out, int32_t* iters, uint32_t* status,
+                       void* stream) {
+  int rc = check_batch(b);
+  if (rc != SHAPE_OK) return rc;
+  if ((profile != 0 && profile != 1) || !(tol >= 0.0) || max_iter < 0) return SHAPE_EINVAL;
+  if (b->n == 0) return SHAPE_OK;
+  if (!rec || !out || !iters || !status) return SHAPE_EINVAL;
+  return from_hip(
+      launch_stars(*b, profile, rec, tol, max_iter, out, iters, status, (hipStream_t)stream));
+}
+
 int shape_queue_default_cfg(shape_queue_cfg* c) {
   if (!c) return SHAPE_EINVAL;
   c->team = 1;

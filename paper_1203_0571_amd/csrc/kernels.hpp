@@ -31,6 +31,10 @@ hipError_t launch_queue_finish(const shape_batch& b, const KOpts& o, void* ws, f
                                float* chi2, float* perr, int32_t* iters, uint32_t* status,
                                int32_t* sweeps, hipStream_t stream);
 
+hipError_t launch_stars(const shape_batch& b, int profile, const float* rec, double tol,
+                        int max_iter, float* out, int32_t* iters, uint32_t* status,
+                        hipStream_t stream);
+
 hipError_t launch_chi2(const shape_batch& b, const float* params, const float* grad_chi2,
                        float* chi2, float* grad_p, float* jtj, float* jtr, bool grad,
                        hipStream_t stream);

@@ -113,3 +113,69 @@ def test_unsupported_mask_and_empty_batch(shape):
     assert L.shape_moments(C.byref(e), C.byref(o), None, None, None, None, None) == shape.OK
     assert L.shape_fit_sersic(C.byref(e), C.byref(o), None, None, None, None, None, None, None,
                               None, None) == shape.OK
+
+
+def test_chi2_argument_errors(shape):
+    L = shape.lib
+    out = C.c_void_p(0x3000)
+    b = _batch(shape)
+    assert L.shape_chi2_fwd(C.byref(b), None, out, None) == shape.EINVAL
+    assert L.shape_chi2_fwd(C.byref(b), out, None, None) == shape.EINVAL
+    assert L.shape_chi2_bwd(C.byref(b), out, None, None, None, None, None, None) == shape.EINVAL
+    bad = _batch(shape, side0=200)
+    assert L.shape_chi2_fwd(C.byref(bad), out, out, None) == shape.EINVAL
+    e = _batch(shape, n=0, pixels=None, sigma=None)
+    assert L.shape_chi2_fwd(C.byref(e), None, None, None) == shape.OK
+    assert L.shape_chi2_bwd(C.byref(e), None, None, None, None, None, None, None) == shape.OK
+
+
+def test_queue_argument_errors(shape):
+    L = shape.lib
+    out = C.c_void_p(0x3000)
+    b = _batch(shape)
+    o = shape.default_opts()
+    c = shape.queue_cfg()
+    assert c.team == 1 and c.grid == 0
+    need = shape.queue_workspace_bytes(b.n)
+    assert need >= b.n * 448
+    assert shape.queue_workspace_bytes(10 ** 6) > 400 * 10 ** 6
+    nb = C.c_size_t()
+    assert L.shape_queue_workspace_bytes(-1, C.byref(nb)) == shape.EINVAL
+    # workspace too small
+    assert L.shape_queue_start(C.byref(b), C.byref(o), C.byref(c), None, out, out, need - 1,
+                               None) == shape.ENOMEM
+    assert L.shape_queue_step(C.byref(b), C.byref(o), C.byref(c), out, need - 1, None) == shape.ENOMEM
+    # missing workspace, missing starting point, bad team sizes
+    assert L.shape_queue_step(C.byref(b), C.byref(o), C.byref(c), None, need, None) == shape.EINVAL
+    assert L.shape_queue_start(C.byref(b), C.byref(o), C.byref(c), None, None, out, need,
+                               None) == shape.EINVAL
+    for team, side in [(3, 64), (2, 3), (4, 200), (0, 64)]:
+        cc = shape.queue_cfg(team=team, team_min_side=side)
+        assert L.shape_queue_step(C.byref(b), C.byref(o), C.byref(cc), out, need,
+                                  None) == shape.EINVAL
+    # the 4-parameter mask runs one wave per stamp only
+    o4 = shape.default_opts(free_mask=0xF0)
+    c2 = shape.queue_cfg(team=2, team_min_side=64)
+    assert L.shape_queue_step(C.byref(b), C.byref(o4), C.byref(c2), out, need,
+                              None) == shape.EUNSUPPORTED
+    g = C.c_void_p()
+    assert L.shape_queue_graph_create(C.byref(b), C.byref(o), C.byref(c), out, need - 1,
+                                      C.byref(g)) == shape.ENOMEM
+    assert L.shape_queue_graph_launch(None, None) == shape.EINVAL
+    assert L.shape_queue_graph_destroy(None) == shape.EINVAL
+    e = _batch(shape, n=0, pixels=None, sigma=None)
+    assert L.shape_queue_step(C.byref(e), C.byref(o), C.byref(c), None, 0, None) == shape.OK
+
+
+def test_star_moments_argument_errors(shape):
+    L = shape.lib
+    out = C.c_void_p(0x3000)
+    b = _batch(shape)
+    assert L.shape_star_moments(C.byref(b), 2, out, 1e-4, 20, out, out, out, None) == shape.EINVAL
+    assert L.shape_star_moments(C.byref(b), 0, out, -1.0, 20, out, out, out, None) == shape.EINVAL
+    assert L.shape_star_moments(C.byref(b), 0, out, 1e-4, -1, out, out, out, None) == shape.EINVAL
+    assert L.shape_star_moments(C.byref(b), 1, None, 1e-4, 20, out, out, out, None) == shape.EINVAL
+    assert L.shape_star_moments(C.byref(b), 1, out, 1e-4, 20, out, None, out, None) == shape.EINVAL
+    assert L.shape_star_moments(None, 1, out, 1e-4, 20, out, out, out, None) == shape.EINVAL
+    e = _batch(shape, n=0, pixels=None, sigma=None)
+    assert L.shape_star_moments(C.byref(e), 0, None, 1e-4, 20, None, None, None, None) == shape.OK

@@ -98,3 +98,23 @@ def test_queue_caps_and_empty(shape):
     e = shape.DeviceBatch(pixels=torch.zeros(0, device="cuda"), sigma=torch.zeros(0, device="cuda"),
                           side0=16)
     assert shape.fit_queue(e)["p"].shape == (0, 8)
+
+
+def test_autotuner_picks_a_measured_candidate(shape, tmp_path, monkeypatch):
+    from paper_1203_0571_amd import autotune
+    monkeypatch.setenv("SHAPE_TUNE_CACHE", str(tmp_path / "tune.json"))
+    b = synth.make("uneven", count=2048)
+    db = shape.DeviceBatch.from_host(b, "cuda:0")
+    o = shape.default_opts()
+    rec = _moments(shape, db, o)
+    cfg, timings = autotune.tune_queue(db, rec, o, sample=1024)
+    assert len(timings) == len(autotune.CANDIDATES)
+    best = min(timings, key=lambda t: t["ms"])["cfg"]
+    assert (cfg.team, cfg.team_min_side) == (best["team"], best["team_min_side"])
+    cfg2, t2 = autotune.tune_queue(db, rec, o, sample=1024)      # served from the cache
+    assert (cfg2.team, cfg2.team_min_side) == (cfg.team, cfg.team_min_side) and t2 == timings
+    q = shape.fit_queue(db, rec=rec, opts=o, cfg=cfg)
+    f = shape.fit_sersic(db, rec=rec, opts=o)
+    conv_q = ((q["status"] & 1) != 0).float().mean().item()
+    conv_f = ((f["status"] & 1) != 0).float().mean().item()
+    assert abs(conv_q - conv_f) < 0.02

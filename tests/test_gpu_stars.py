@@ -1,0 +1,98 @@
+"""GPU star sizes from weighted moments (Sec. 4.2) against the FP64 oracle.
+
+Both sides run their own chain: starting estimates, centroid, joint centre and
+ellipticity, then the star estimator about that centre.  Stamps where both
+report convergence are compared to relative 1e-3 on the size, beta and I0
+(the bar of the profile fit), and the status words must agree on most stamps
+(a stamp near the stopping threshold may take one step more on one side)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import oracle_opts_like
+
+pytestmark = pytest.mark.gpu
+
+BAR_REL = 1e-3
+
+
+def _oracle_chain(batch, profile, tol, max_iter, o):
+    kind = oracle.SERSIC if profile == 0 else oracle.MOFFAT
+    out = np.full((batch.n, 4), np.nan)
+    st = np.zeros(batch.n, np.uint32)
+    its = np.zeros(batch.n, np.int32)
+    for i in range(batch.n):
+        img = batch.stamp(i)
+        side = img.shape[0]
+        ini = oracle.init(img)
+        x, y, _, _ = oracle.centroid(img, ini["sky0"], ini["sigw"], ini["imax"] % side,
+                                     ini["imax"] // side, o)
+        mo, _, _ = oracle.moments(img, ini["sky0"], ini["sigw"], ini["r50"], x, y, o)
+        w0 = ini["sigw"] if profile == 0 else ini["r50"] / math.sqrt(math.sqrt(2.0) - 1.0)
+        r = oracle.star_moments(img, ini["sky0"], mo[0], mo[1], mo[2:4], kind, w0, tol, max_iter)
+        out[i] = (r["size"], r["beta"], r["I0"], r["r0"])
+        st[i], its[i] = r["status"], r["iters"]
+    return out, its, st
+
+
+def _gpu_chain(batch, profile, tol, max_iter):
+    import torch
+    import paper_1203_0571_amd as shape
+    db = shape.DeviceBatch.from_host(batch, "cuda:0")
+    rec0, _, _ = shape.centroid(db)
+    rec1, _, _ = shape.moments(db, rec0)
+    out, it, st = shape.star_moments(db, rec1, profile, tol, max_iter)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64), it.cpu().numpy(), \
+        st.cpu().numpy().astype(np.uint32)
+
+
+@pytest.mark.parametrize("workload,profile,tol,max_iter", [
+    ("plain32", 0, 1e-4, 20),     # the paper's stopping rule
+    ("plain32", 0, 1e-7, 200),
+    ("stars32", 1, 1e-4, 20),
+    ("stars32", 1, 1e-7, 200),
+])
+def test_star_moments_vs_oracle(workload, profile, tol, max_iter):
+    import paper_1203_0571_amd as shape
+    batch = synth.make(workload, 256)
+    o = oracle_opts_like(shape.default_opts())
+    ref, it_o, st_o = _oracle_chain(batch, profile, tol, max_iter, o)
+    got, it_g, st_g = _gpu_chain(batch, profile, tol, max_iter)
+    both = ((st_g & oracle.CONVERGED) != 0) & ((st_o & oracle.CONVERGED) != 0)
+    print(workload, profile, "conv gpu", int(((st_g & 1) != 0).sum()), "oracle",
+          int(((st_o & 1) != 0).sum()), "both", int(both.sum()),
+          "status agree", float((st_g == st_o).mean()))
+    assert both.sum() >= 0.5 * batch.n
+    assert (st_g == st_o).mean() >= 0.95
+    cols = [0, 2, 3] if profile == 0 else [0, 1, 2, 3]
+    rel = np.abs(got[both][:, cols] / ref[both][:, cols] - 1.0)
+    print("max rel", rel.max(0))
+    assert rel.max() <= BAR_REL
+    if profile == 0:
+        assert np.all(got[:, 1] == 0.0)
+
+
+def test_star_moments_edge_cases():
+    """Zero iterations, and a non-finite record entry."""
+    import torch
+    import paper_1203_0571_amd as shape
+    batch = synth.make("stars32", 8)
+    db = shape.DeviceBatch.from_host(batch, "cuda:0")
+    rec, _, _ = shape.centroid(db)
+    rec, _, _ = shape.moments(db, rec)
+    out, it, st = shape.star_moments(db, rec, 1, 1e-4, 0)
+    torch.cuda.synchronize()
+    assert np.all(it.cpu().numpy() == 0)
+    assert np.all((st.cpu().numpy() & oracle.MAX_ITER) != 0)
+    bad = rec.clone()
+    bad[3, 2] = float("nan")
+    out, it, st = shape.star_moments(db, bad, 1)
+    torch.cuda.synchronize()
+    s = st.cpu().numpy()
+    assert s[3] & oracle.BAD_INPUT
+    assert np.isnan(out[3].cpu().numpy()).all()
+    assert np.all(np.isfinite(out[[0, 1, 2, 4, 5, 6, 7]].cpu().numpy()))

@@ -83,6 +83,10 @@ def lib():
         L.orc_pipeline.restype = C.c_int
         L.orc_pipeline.argtypes = [C.c_int64, d, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(Opts), d, d, d, d, C.c_void_p, C.c_void_p, C.c_int]
+        L.orc_star_pipeline.restype = C.c_int
+        L.orc_star_pipeline.argtypes = [C.c_int64, d, C.c_void_p, C.c_void_p, C.POINTER(Opts),
+                                        C.c_int, C.c_double, C.c_int, d, C.c_void_p,
+                                        C.c_void_p, C.c_int]
         _lib = L
     return _lib
 
@@ -228,3 +232,20 @@ def pipeline(batch, o=None, threads=0, pixels_f64=None):
                               mdl.ctypes.data, C.byref(o), _dp(xy), _dp(mom), _dp(p), _dp(c2),
                               iters.ctypes.data, status.ctypes.data, int(threads))
     return dict(xy=xy, mom=mom, p=p, chi2=c2, iters=iters, status=status, threads=used)
+
+
+def star_pipeline(batch, kind, tol=1e-4, max_iter=20, o=None, threads=0):
+    """Star sizes over a synth.Batch (Sec. 4.2) after the centroid and moments
+    stages; out[n, 6] = (size, beta, I0, r0, r2, r4)."""
+    o = o or opts()
+    n = batch.n
+    pix = _f64(batch.dequantised_f64())
+    offs = np.ascontiguousarray(batch.offsets, np.int64)
+    sides = np.ascontiguousarray(batch.sides, np.int32)
+    out = np.zeros((n, 6))
+    iters = np.zeros(n, np.int32)
+    status = np.zeros(n, np.uint32)
+    used = lib().orc_star_pipeline(n, _dp(pix), offs.ctypes.data, sides.ctypes.data, C.byref(o),
+                                   int(kind), float(tol), int(max_iter), _dp(out),
+                                   iters.ctypes.data, status.ctypes.data, int(threads))
+    return dict(out=out, iters=iters, status=status, threads=used)

@@ -114,6 +114,14 @@ int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
                  const orc_opts* o, double* xy, double* mom, double* p,
                  double* chi2, int32_t* iters, uint32_t* status, int threads);
 
+/* Star sizes over a batch (Sec. 4.2), OpenMP over stamps; returns threads
+ * used.  Per stamp: starting estimates, centroid, joint centre + ellipticity,
+ * then orc_star_moments of the given kind; out[6] as there, iters, status. */
+int orc_star_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
+                      const int32_t* sides, const orc_opts* o, int kind, double tol,
+                      int max_iter, double* out, int32_t* iters, uint32_t* status,
+                      int threads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -80,8 +80,9 @@ WORKLOADS = {
                          description="65,536 x 64x64 FP32 Sersic galaxies"),
     "sersic64h": Workload("sersic64h", 262_144, 64, "sersic", storage="f16",
                           description="262,144 x 64x64 Sersic galaxies, FP16 + per-stamp scale"),
-    "stars32": Workload("stars32", 1_000, 32, "moffat",
-                        description="1,000 x 32x32 FP32 Moffat stars, beta U(2.5,5), FWHM U(2,5)"),
+    "stars32": Workload("stars32", 1_048_576, 32, "moffat",
+                        description="1,048,576 x 32x32 FP32 Moffat stars, beta U(2.5,5), "
+                                    "FWHM U(2,5)"),
 }
 
 

@@ -89,3 +89,24 @@ def test_moffat_inversion_exact_at_matched_weight():
     assert r["r0"] == pytest.approx(1000.0 * math.pi * rd ** 2 / (beta + 2), rel=1e-5)
     assert r["beta"] == pytest.approx(beta, rel=1e-4)
     assert r["size"] == pytest.approx(rd, rel=1e-4)
+
+
+@pytest.mark.parametrize("kind", [oracle.SERSIC, oracle.MOFFAT])
+def test_batched_chain_matches_per_stamp_calls(kind):
+    """orc_star_pipeline is the per-stamp chain init -> centroid -> moments ->
+    star estimator, run over a batch."""
+    b = synth.make("stars32", 24)
+    o = oracle.opts()
+    r = oracle.star_pipeline(b, kind, 1e-4, 20, o, threads=2)
+    for i in range(b.n):
+        img = b.stamp(i)
+        ini = oracle.init(img)
+        x, y, _, _ = oracle.centroid(img, ini["sky0"], ini["sigw"], ini["imax"] % 32,
+                                     ini["imax"] // 32, o)
+        mo, _, _ = oracle.moments(img, ini["sky0"], ini["sigw"], ini["r50"], x, y, o)
+        w0 = ini["sigw"] if kind == oracle.SERSIC else ini["r50"] / math.sqrt(math.sqrt(2) - 1)
+        s = oracle.star_moments(img, ini["sky0"], mo[0], mo[1], mo[2:4], kind, w0)
+        assert s["status"] == r["status"][i]
+        assert s["iters"] == r["iters"][i]
+        np.testing.assert_array_equal(
+            np.array([s["size"], s["beta"], s["I0"], s["r0"], s["r2"], s["r4"]]), r["out"][i])

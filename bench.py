@@ -34,6 +34,14 @@ if ROOT not in sys.path:
 # parameters, Sersic): model + residual 31 FLOP, Jacobian 25, J^T r and chi^2
 # 17, J^T J 63 (FMA = 2 FLOP), plus 4 transcendentals counted as 1 each.
 FLOP_PER_PIXEL_SWEEP = 140.0
+# Per pixel per iteration of the other stages (FMA = 2, transcendental = 1):
+# centroid sweep: offsets 2, R^2 3, weight 2, f W 2, three sums 5 -> 14;
+# moments sweep: offsets 2, products 3, R^2 5, weight 2, f W 2, eleven
+# moment sums 21 -> 35; star step (R^2 and f formed once per pixel): weight
+# 5 (Moffat) or 2 (Gaussian), products 3, three sums 3 -> 11 (Moffat).
+FLOP_PER_PIXEL_CENTROID = 14.0
+FLOP_PER_PIXEL_MOMENTS = 35.0
+FLOP_PER_PIXEL_STAR_MOFFAT = 11.0
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s; one
 # FP32 or FP64 FMA (2 FLOP) per lane-op without packed FP32 math.
 ALU_PEAK_TFLOPS = 78.6
@@ -73,9 +81,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
-    ap.add_argument("--workload", default="sersic64h", choices=["sersic64h", "uneven"],
+    ap.add_argument("--workload", default="sersic64h", choices=["sersic64h", "uneven", "stars32"],
                     help="uneven: 1,000,000 stamps of side 16-128 (80%% Sersic, 20%% Moffat), "
-                         "fused fit vs autotuned work queue")
+                         "fused fit vs autotuned work queue; stars32: 1,048,576 32x32 Moffat "
+                         "stars, sizes from weighted moments")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -91,6 +100,8 @@ def main():
 
     if args.workload == "uneven":
         return bench_uneven(args)
+    if args.workload == "stars32":
+        return bench_stars(args)
     forms = [f for f in args.forms.split(",") if f]
     # Stamps are generated (in worker processes) before this process touches
     # the GPU, so no worker is forked from a process with an initialised runtime.
@@ -321,6 +332,97 @@ def bench_uneven(args):
                          "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
                          "traffic": None, "launch_ms": round(r["fit_ms"], 3)}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_stars(args):
+    """Star sizes (Sec. 4.2) on 32x32 Moffat stars: centroid, joint centre and
+    ellipticity, then the Moffat weighted-moment estimator (beta, rd, I0)."""
+    import numpy as np
+
+    import synth
+
+    t = time.time()
+    b = synth.make("stars32", count=args.count)
+    log("generated %d stars (32x32) in %.1f s" % (b.n, time.time() - t))
+
+    import torch
+
+    import paper_1203_0571_amd as shape
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    db = shape.DeviceBatch.from_host(b, dev)
+    opts = shape.default_opts()
+    npix = 32 * 32
+
+    def step(ev=None):
+        if ev:
+            ev[0].record()
+        r0, i0, _ = shape.centroid(db, opts)
+        if ev:
+            ev[1].record()
+        r1, i1, _ = shape.moments(db, r0, opts)
+        if ev:
+            ev[2].record()
+        out = shape.star_moments(db, r1, shape.STAR_MOFFAT, 1e-4, 20)
+        if ev:
+            ev[3].record()
+        return i0, i1, out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        i0, i1, (out, i2, st) = step(evs[k])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = {name: float(np.mean([e[q].elapsed_time(e[q + 1]) for e in evs]))
+          for q, name in enumerate(("centroid", "moments", "star_moments"))}
+    its = [x.cpu().numpy().astype(np.float64) for x in (i0, i1, i2)]
+    flop = {"centroid": its[0].sum() * npix * FLOP_PER_PIXEL_CENTROID,
+            "moments": its[1].sum() * npix * FLOP_PER_PIXEL_MOMENTS,
+            "star_moments": its[2].sum() * npix * FLOP_PER_PIXEL_STAR_MOFFAT}
+    stv = st.cpu().numpy()
+    conv = float(((stv & shape.ST_CONVERGED) != 0).mean())
+    dom = max(ms, key=ms.get)
+    achieved = flop[dom] / (ms[dom] * 1e-3) / 1e12
+    log("stars: %.0f objects/s; %s; converged %.4f"
+        % (b.n * args.steps / el, {k: round(v, 3) for k, v in ms.items()}, conv))
+    line = {"metric": "star sizes measured/sec (32x32 Moffat stars, weighted moments)",
+            "value": round(b.n * args.steps / el, 1), "unit": "objects/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(el / args.steps * 1e3, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "stars32: %d x 32x32 Moffat stars, seed 0" % b.n,
+                       "kernel_ms": {k: round(v, 4) for k, v in ms.items()},
+                       "mean_iters": {k: round(float(x.mean()), 3) for k, x in
+                                      zip(("centroid", "moments", "star_moments"), its)},
+                       "converged_fraction": round(conv, 4)},
+            "roofline": {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
+                         "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                         "launch_ms": round(ms[dom], 4)}}
+    if not args.no_cpu:
+        import oracle
+        m = min(args.cpu_sample * 16, b.n)
+        t = time.perf_counter()
+        ref = oracle.star_pipeline(b.head(m), oracle.MOFFAT, 1e-4, 20)
+        cpu_s = time.perf_counter() - t
+        line["cpu_baseline"] = {"value": round(m / cpu_s, 2), "unit": "objects/s",
+                                "cores": int(ref["threads"]), "kind": "oracle",
+                                "sample": "first %d stars, FP64 oracle chain, %.1f s" % (m, cpu_s)}
+        g = out[:m].cpu().numpy().astype(np.float64)
+        both = ((stv[:m] & 1) != 0) & ((ref["status"] & 1) != 0)
+        rel = np.abs(g[both][:, :3] / ref["out"][both][:, :3] - 1)
+        line["parity"] = {"sample": m, "both_converged": int(both.sum()),
+                          "status_agree": float((stv[:m] == ref["status"]).mean()),
+                          "max_rel_rd": float(rel[:, 0].max()) if both.any() else None,
+                          "max_rel_beta": float(rel[:, 1].max()) if both.any() else None,
+                          "max_rel_i0": float(rel[:, 2].max()) if both.any() else None,
+                          "within_1e-3": float((rel.max(1) <= 1e-3).mean()) if both.any() else None}
     print(json.dumps(line), flush=True)
 
 

@@ -10,12 +10,45 @@
 //            rd = sqrt(r2 / r0 (beta + 1)), I0 = r0 (beta + 2) / (pi rd^2)
 //            (exact when w = rd);
 // and sets w to the new size until the fractional change is below tol.
+//
+// Only w changes from step to step, so f and R^2 of every pixel are formed
+// once.  Stamps of up to 64 x kCache pixels keep them in registers (pixel
+// lane + 64 q in slot q) and read HBM once; larger stamps recompute them from
+// the stamp on every step.
 #include "kernels.hpp"
 
 namespace shape {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kCache = 16;   // side <= 32
+
+struct StarGeom {
+  float x0, y0, a11, a12, a22, invD, sky;
+};
+
+__device__ inline float star_r2(const StarGeom& G, int i, int j) {
+  const float t1 = (float)j - G.x0, t2 = (float)i - G.y0;
+  const float v1 = fmaf(G.a11, t1, G.a12 * t2), v2 = fmaf(G.a12, t1, G.a22 * t2);
+  return fmaf(v1, v1, v2 * v2) * G.invD;
+}
+
+template <int PROFILE>
+__device__ inline void star_accumulate(float f, float R2, float c, double& s0, double& s2,
+                                       double& s4) {
+  float W;
+  if constexpr (PROFILE == 0) {
+    W = fast_exp2(-R2 * c);
+  } else {
+    const float ib = fast_rcp(fmaf(R2, c, 1.0f));
+    W = ib * ib * ib;
+  }
+  const float fw = f * W;
+  const float fw2 = fw * R2;
+  s0 += (double)fw;
+  s2 += (double)fw2;
+  s4 += (double)(fw2 * R2);
+}
 
 template <int DT, int PROFILE>
 __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float* rec, double tol,
@@ -39,11 +72,30 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
       }
       continue;
     }
-    const float x0 = r[SHAPE_REC_X0], y0 = r[SHAPE_REC_Y0];
     const double g1 = r[SHAPE_REC_E1], g2 = r[SHAPE_REC_E2];
-    const float a11 = (float)(1.0 - g1), a12 = (float)(-g2), a22 = (float)(1.0 + g1);
-    const float invD = (float)(1.0 / (1.0 - g1 * g1 - g2 * g2));
-    const float sky = r[SHAPE_REC_SKY0];
+    StarGeom G;
+    G.x0 = r[SHAPE_REC_X0];
+    G.y0 = r[SHAPE_REC_Y0];
+    G.a11 = (float)(1.0 - g1);
+    G.a12 = (float)(-g2);
+    G.a22 = (float)(1.0 + g1);
+    G.invD = (float)(1.0 / (1.0 - g1 * g1 - g2 * g2));
+    G.sky = r[SHAPE_REC_SKY0];
+    const bool cached = st.npix <= kWave * kCache;
+    float cf[kCache], cr[kCache];
+    if (cached) {
+#pragma unroll
+      for (int q = 0; q < kCache; ++q) {
+        const int k = lane + kWave * q;
+        cf[q] = 0.0f;
+        cr[q] = 0.0f;
+        if (k < st.npix) {
+          const int i = k / st.side;
+          cf[q] = load_px<DT>(b.pixels, st.off, k, st.scale) - G.sky;
+          cr[q] = star_r2(G, i, k - i * st.side);
+        }
+      }
+    }
     // starting width: the Gaussian of half-light radius r50, or the beta = 3
     // Moffat of that half-light radius (r50 = rd sqrt(2^(1/2) - 1))
     double w = PROFILE == 0 ? (double)r[SHAPE_REC_SIGW]
@@ -54,23 +106,15 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
     while (it < max_iter) {
       const float c = (float)(PROFILE == 0 ? kLog2e / (2.0 * w * w) : 1.0 / (w * w));
       double s0 = 0.0, s2 = 0.0, s4 = 0.0;
-      for_pixels(st.side, [&](int k, int i, int j) {
-        const float d = load_px<DT>(b.pixels, st.off, k, st.scale);
-        const float t1 = (float)j - x0, t2 = (float)i - y0;
-        const float v1 = fmaf(a11, t1, a12 * t2), v2 = fmaf(a12, t1, a22 * t2);
-        const float R2 = fmaf(v1, v1, v2 * v2) * invD;
-        float W;
-        if constexpr (PROFILE == 0) {
-          W = fast_exp2(-R2 * c);
-        } else {
-          const float ib = fast_rcp(fmaf(R2, c, 1.0f));
-          W = ib * ib * ib;
-        }
-        const float fw = (d - sky) * W;
-        s0 += (double)fw;
-        s2 += (double)(fw * R2);
-        s4 += (double)(fw * R2 * R2);
-      });
+      if (cached) {
+#pragma unroll
+        for (int q = 0; q < kCache; ++q) star_accumulate<PROFILE>(cf[q], cr[q], c, s0, s2, s4);
+      } else {
+        for_pixels(st.side, [&](int k, int i, int j) {
+          const float f = load_px<DT>(b.pixels, st.off, k, st.scale) - G.sky;
+          star_accumulate<PROFILE>(f, star_r2(G, i, j), c, s0, s2, s4);
+        });
+      }
       s0 = wave_sum(s0);
       s2 = wave_sum(s2);
       s4 = wave_sum(s4);
@@ -115,27 +159,29 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
   }
 }
 
+template <int DT, int PROFILE>
+void launch_one(const shape_batch& b, const float* rec, double tol, int max_iter, float* out,
+                int32_t* iters, uint32_t* status, hipStream_t stream) {
+  const int64_t grid = b.n < (1ll << 30) ? b.n : (1ll << 30);
+  hipLaunchKernelGGL((star_kernel<DT, PROFILE>), dim3((unsigned)grid), dim3(kWave), 0, stream, b,
+                     rec, tol, max_iter, out, iters, status);
+}
+
 }  // namespace
 
 hipError_t launch_stars(const shape_batch& b, int profile, const float* rec, double tol,
                         int max_iter, float* out, int32_t* iters, uint32_t* status,
                         hipStream_t stream) {
-  const int64_t grid = b.n < (1ll << 30) ? b.n : (1ll << 30);
-  const dim3 g((unsigned)grid), t(kWave);
   if (b.dtype == SHAPE_F32) {
     if (profile == 0)
-      hipLaunchKernelGGL((star_kernel<SHAPE_F32, 0>), g, t, 0, stream, b, rec, tol, max_iter, out,
-                         iters, status);
+      launch_one<SHAPE_F32, 0>(b, rec, tol, max_iter, out, iters, status, stream);
     else
-      hipLaunchKernelGGL((star_kernel<SHAPE_F32, 1>), g, t, 0, stream, b, rec, tol, max_iter, out,
-                         iters, status);
+      launch_one<SHAPE_F32, 1>(b, rec, tol, max_iter, out, iters, status, stream);
   } else {
     if (profile == 0)
-      hipLaunchKernelGGL((star_kernel<SHAPE_F16_SCALED, 0>), g, t, 0, stream, b, rec, tol,
-                         max_iter, out, iters, status);
+      launch_one<SHAPE_F16_SCALED, 0>(b, rec, tol, max_iter, out, iters, status, stream);
     else
-      hipLaunchKernelGGL((star_kernel<SHAPE_F16_SCALED, 1>), g, t, 0, stream, b, rec, tol,
-                         max_iter, out, iters, status);
+      launch_one<SHAPE_F16_SCALED, 1>(b, rec, tol, max_iter, out, iters, status, stream);
   }
   return hipGetLastError();
 }

@@ -5,8 +5,6 @@ ellipticity, then the star estimator about that centre.  Stamps where both
 report convergence are compared to relative 1e-3 on the size, beta and I0
 (the bar of the profile fit), and the status words must agree on most stamps
 (a stamp near the stopping threshold may take one step more on one side)."""
-import math
-
 import numpy as np
 import pytest
 
@@ -21,21 +19,8 @@ BAR_REL = 1e-3
 
 def _oracle_chain(batch, profile, tol, max_iter, o):
     kind = oracle.SERSIC if profile == 0 else oracle.MOFFAT
-    out = np.full((batch.n, 4), np.nan)
-    st = np.zeros(batch.n, np.uint32)
-    its = np.zeros(batch.n, np.int32)
-    for i in range(batch.n):
-        img = batch.stamp(i)
-        side = img.shape[0]
-        ini = oracle.init(img)
-        x, y, _, _ = oracle.centroid(img, ini["sky0"], ini["sigw"], ini["imax"] % side,
-                                     ini["imax"] // side, o)
-        mo, _, _ = oracle.moments(img, ini["sky0"], ini["sigw"], ini["r50"], x, y, o)
-        w0 = ini["sigw"] if profile == 0 else ini["r50"] / math.sqrt(math.sqrt(2.0) - 1.0)
-        r = oracle.star_moments(img, ini["sky0"], mo[0], mo[1], mo[2:4], kind, w0, tol, max_iter)
-        out[i] = (r["size"], r["beta"], r["I0"], r["r0"])
-        st[i], its[i] = r["status"], r["iters"]
-    return out, its, st
+    r = oracle.star_pipeline(batch, kind, tol, max_iter, o)
+    return r["out"][:, :4], r["iters"], r["status"]
 
 
 def _gpu_chain(batch, profile, tol, max_iter):

@@ -83,6 +83,9 @@ def lib():
         L.orc_pipeline.restype = C.c_int
         L.orc_pipeline.argtypes = [C.c_int64, d, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(Opts), d, d, d, d, C.c_void_p, C.c_void_p, C.c_int]
+        L.orc_frame_detect.argtypes = [d, C.c_int, C.c_int, C.c_int, d, d, d,
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p,
+                                       C.POINTER(C.c_uint32)]
         L.orc_star_pipeline.restype = C.c_int
         L.orc_star_pipeline.argtypes = [C.c_int64, d, C.c_void_p, C.c_void_p, C.POINTER(Opts),
                                         C.c_int, C.c_double, C.c_int, d, C.c_void_p,
@@ -249,3 +252,22 @@ def star_pipeline(batch, kind, tol=1e-4, max_iter=20, o=None, threads=0):
                                    int(kind), float(tol), int(max_iter), _dp(out),
                                    iters.ctypes.data, status.ctypes.data, int(threads))
     return dict(out=out, iters=iters, status=status, threads=used)
+
+
+def frame_detect(img, max_side=128):
+    """Front end on one frame: sky, r50, flux, peak (x, y), box (x0, y0, side)."""
+    img = _f64(img)
+    H, W = img.shape
+    sky, r50, flux = C.c_double(), C.c_double(), C.c_double()
+    px, py, st = C.c_int(), C.c_int(), C.c_uint32(0)
+    box = np.zeros(3, np.int32)
+    lib().orc_frame_detect(_dp(img), H, W, int(max_side), C.byref(sky), C.byref(r50),
+                           C.byref(flux), C.byref(px), C.byref(py), box.ctypes.data, C.byref(st))
+    return dict(sky=sky.value, r50=r50.value, flux=flux.value, peak=(px.value, py.value),
+                box=tuple(int(v) for v in box), status=st.value)
+
+
+def frame_cut(img, box):
+    """The cut-out square of a frame as a copy."""
+    x0, y0, s = box
+    return np.array(img[y0:y0 + s, x0:x0 + s], dtype=np.float64, copy=True)

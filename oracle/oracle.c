@@ -880,3 +880,88 @@ int orc_star_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
   }
   return used;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Front end on whole frames (Sec. 4.1, the paragraph on the starting        */
+/* point): the brightest pixel of the frame, r50 from summing the pixels     */
+/* outward from it until half the total flux, and a square of side 6 r50     */
+/* cut out around it.  Same readings as the stamp estimates (border-mean     */
+/* sky, integer-radius rings, interpolated first crossing).  Further         */
+/* readings: the side is 6 r50 rounded to the nearest integer (halves away   */
+/* from zero), clamped to [4, min(max_side, H, W)]; the square starts at     */
+/* the peak minus side/2 (integer division) in each axis, shifted to lie     */
+/* inside the frame; with no positive total flux r50 = min(H, W) / 8.        */
+/* ------------------------------------------------------------------------ */
+void orc_frame_detect(const double* img, int H, int W, int max_side, double* sky0,
+                      double* r50, double* flux, int* peak_x, int* peak_y, int* box,
+                      uint32_t* status) {
+  for (size_t k = 0; k < (size_t)H * W; ++k) {
+    if (!isfinite(img[k])) {
+      /* a frame with a NaN or Inf pixel yields no cut-out (side 0) */
+      *status = ORC_NONFINITE_INPUT;
+      *sky0 = *r50 = *flux = NAN;
+      *peak_x = *peak_y = -1;
+      box[0] = box[1] = box[2] = 0;
+      return;
+    }
+  }
+  double bsum = 0.0;
+  for (int i = 0; i < H; ++i)
+    for (int j = 0; j < W; ++j)
+      if (i == 0 || j == 0 || i == H - 1 || j == W - 1) bsum += img[(size_t)i * W + j];
+  double sky = bsum / (2.0 * W + 2.0 * H - 4.0);
+  size_t best = 0;
+  for (size_t k = 1; k < (size_t)H * W; ++k)
+    if (img[k] > img[best]) best = k;
+  int i0 = (int)(best / W), j0 = (int)(best % W);
+  int nbins = (int)ceil(sqrt((double)H * H + (double)W * W)) + 2;
+  double* ring = (double*)calloc((size_t)nbins, sizeof(double));
+  double F = 0.0;
+  for (int i = 0; i < H; ++i) {
+    for (int j = 0; j < W; ++j) {
+      long d2 = (long)(i - i0) * (i - i0) + (long)(j - j0) * (j - j0);
+      /* smallest integer r with r^2 >= d2 */
+      int r = (int)ceil(sqrt((double)d2));
+      while ((long)r * r < d2) ++r;
+      while (r > 0 && (long)(r - 1) * (r - 1) >= d2) --r;
+      double f = img[(size_t)i * W + j] - sky;
+      ring[r] += f;
+      F += f;
+    }
+  }
+  int mind = H < W ? H : W;
+  double half = 0.5 * F, rr = 0.125 * mind;
+  *status = 0;
+  if (F > 0.0) {
+    double prev = 0.0, cum = ring[0];
+    for (int r = 1; r < nbins; ++r) {
+      cum += ring[r];
+      if (cum >= half) {
+        rr = (r - 1) + (half - prev) / (cum - prev);
+        break;
+      }
+      prev = cum;
+    }
+  } else {
+    *status |= ORC_NONPOSITIVE_FLUX;
+  }
+  free(ring);
+  int smax = max_side;
+  if (smax > mind) smax = mind;
+  long side = lround(6.0 * rr);
+  if (side < 4) side = 4;
+  if (side > smax) side = smax;
+  int ox = j0 - (int)side / 2, oy = i0 - (int)side / 2;
+  if (ox > W - side) ox = W - (int)side;
+  if (oy > H - side) oy = H - (int)side;
+  if (ox < 0) ox = 0;
+  if (oy < 0) oy = 0;
+  *sky0 = sky;
+  *r50 = rr;
+  *flux = F;
+  *peak_x = j0;
+  *peak_y = i0;
+  box[0] = ox;
+  box[1] = oy;
+  box[2] = (int)side;
+}

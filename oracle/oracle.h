@@ -114,6 +114,14 @@ int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
                  const orc_opts* o, double* xy, double* mom, double* p,
                  double* chi2, int32_t* iters, uint32_t* status, int threads);
 
+/* Front end on a whole H x W frame (Sec. 4.1, starting point): border-mean
+ * sky, brightest pixel, growth-curve r50 about it, and the cut-out square
+ * box = (x origin, y origin, side) with side = round(6 r50) clamped to
+ * [4, min(max_side, H, W)], placed around the peak inside the frame. */
+void orc_frame_detect(const double* img, int H, int W, int max_side, double* sky0,
+                      double* r50, double* flux, int* peak_x, int* peak_y, int* box,
+                      uint32_t* status);
+
 /* Star sizes over a batch (Sec. 4.2), OpenMP over stamps; returns threads
  * used.  Per stamp: starting estimates, centroid, joint centre + ellipticity,
  * then orc_star_moments of the given kind; out[6] as there, iters, status. */

@@ -369,3 +369,93 @@ def make(workload, count=None, start=0, seed=0, storage=None, workers=None):
                  np.concatenate([ch.sigma for ch in chunks]),
                  np.concatenate([ch.model for ch in chunks]),
                  np.concatenate([ch.truth for ch in chunks]), scale, start)
+
+
+# ---------------------------------------------------------------------------
+# Whole frames with one galaxy each (the paper's simulations place each galaxy
+# on a 512 x 512 grid and cut a stamp of side 6 r50 around it).
+# ---------------------------------------------------------------------------
+FRAME_SIDE = 512
+FRAME_WINDOW = 128     # the profile is rendered in a 128 x 128 window about its centre
+FRAME_CHUNK = 64
+FRAMES_N = 4096
+
+
+@dataclass
+class Frames:
+    """A stack of equal frames (host numpy arrays)."""
+    pixels: np.ndarray        # float32 [n, H, W]
+    sigma: np.ndarray         # float32 [n]
+    truth: np.ndarray         # float64 [n, 8] (centre in frame pixels)
+    start: int = 0
+
+    @property
+    def n(self):
+        return int(self.pixels.shape[0])
+
+    def head(self, m):
+        m = min(int(m), self.n)
+        return Frames(self.pixels[:m], self.sigma[:m], self.truth[:m], self.start)
+
+
+def _frame_chunk(args):
+    seed, cidx, k = args
+    rng = np.random.default_rng([seed, 0x46524D, cidx])
+    H = W = FRAME_SIDE
+    p = np.zeros((k, 8))
+    p[:, 0] = rng.uniform(128.0, 384.0, k)
+    p[:, 1] = rng.uniform(128.0, 384.0, k)
+    p[:, 2:4] = _draw_e(rng, k, 0.25, 0.7)
+    p[:, 4] = _loguniform(rng, 1.5, 6.0, k)
+    p[:, 5] = rng.uniform(0.5, 4.0, k)
+    flux = _loguniform(rng, 1e4, 1e6, k)
+    snr = _loguniform(rng, 5e3, 5e4, k)
+    p[:, 6] = flux / sersic_flux_factor(p[:, 5], p[:, 4])
+    p[:, 7] = SKY
+    out = np.empty((k, H, W), np.float32)
+    sig = np.empty(k, np.float32)
+    h = FRAME_WINDOW // 2
+    for q in range(k):
+        cx, cy = int(p[q, 0]), int(p[q, 1])
+        win = p[q:q + 1].copy()
+        win[0, 0] -= cx - h
+        win[0, 1] -= cy - h
+        clean = render_sersic(FRAME_WINDOW, win)[0]
+        sig[q] = np.float32(math.sqrt(float((clean ** 2).sum())) / snr[q])
+        frame = SKY + rng.standard_normal((H, W)) * float(sig[q])
+        frame[cy - h:cy + h, cx - h:cx + h] += clean
+        out[q] = frame
+    return out, sig, p
+
+
+def make_frames(count=None, start=0, seed=0, workers=None):
+    """Frames [start, start+count) of the 512 x 512 one-galaxy-per-frame set:
+    Sersic galaxies as the 48x48 set (n U(0.5,4), Re log-U(1.5,6), e_i N(0,0.25)
+    with |e| < 0.7, sky 10), centre U(128,384) on both axes, flux log-U(1e4,1e6),
+    S/N log-U(5e3,5e4) (the sum over a whole frame carries the noise of
+    all its 262,144 pixels, so the total flux needs a high S/N); the profile is rendered in a 128 x 128 window about
+    the centre pixel, noise over the whole frame."""
+    count = FRAMES_N - start if count is None else count
+    if start % FRAME_CHUNK or start < 0 or count < 0 or start + count > FRAMES_N:
+        raise ValueError("range outside the frame set")
+    jobs, c, left = [], start // FRAME_CHUNK, count
+    while left > 0:
+        k = min(FRAME_CHUNK, left)
+        jobs.append((seed, c, k))
+        left -= k
+        c += 1
+    if workers is None:
+        workers = min(len(jobs), int(os.environ.get("SYNTH_WORKERS", min(16, os.cpu_count() or 1))))
+        tmod = sys.modules.get("torch")
+        if tmod is not None and tmod.cuda.is_initialized():
+            workers = 1
+    if workers > 1 and len(jobs) > 1:
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            parts = list(ex.map(_frame_chunk, jobs))
+    else:
+        parts = [_frame_chunk(j) for j in jobs]
+    if not parts:
+        return Frames(np.zeros((0, FRAME_SIDE, FRAME_SIDE), np.float32), np.zeros(0, np.float32),
+                      np.zeros((0, 8)), start)
+    return Frames(np.concatenate([a for a, _, _ in parts]), np.concatenate([b for _, b, _ in parts]),
+                  np.concatenate([t for _, _, t in parts]), start)

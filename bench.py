@@ -42,10 +42,45 @@ FLOP_PER_PIXEL_SWEEP = 140.0
 FLOP_PER_PIXEL_CENTROID = 14.0
 FLOP_PER_PIXEL_MOMENTS = 35.0
 FLOP_PER_PIXEL_STAR_MOFFAT = 11.0
+# MI355X HBM3E: 8 TB/s.
+HBM_PEAK_GBS = 8000.0
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s; one
 # FP32 or FP64 FMA (2 FLOP) per lane-op without packed FP32 math.
 ALU_PEAK_TFLOPS = 78.6
 BARS = dict(x=1e-3, e=1e-4, rel=1e-3)
+
+
+# Sources that make up the fit kernel; the HBM counters in profiles/ are used
+# only while these are unchanged.
+FIT_SOURCES = ["paper_1203_0571_amd/csrc/fit.hip", "paper_1203_0571_amd/csrc/lm.hpp",
+               "paper_1203_0571_amd/csrc/sweep.hpp", "paper_1203_0571_amd/csrc/common.hpp",
+               "paper_1203_0571_amd/csrc/bn_table.h", "paper_1203_0571_amd/csrc/kernels.hpp",
+               "include/shape.h", "paper_1203_0571_amd/build.py"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fit_sersic64h_hbm_traffic.md")
+
+
+def fit_traffic_bytes():
+    """HBM bytes per launch of the FP16 fit from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE in KiB, each scaled by its copy calibration),
+    or None if the summary is missing or the kernel's sources changed since."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    kv = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith("    "):
+            k, v = line.strip().split(":", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in FIT_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if kv.get("source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+            float(kv["write_kib"]) * float(kv["write_scale"])) * 1024.0
 
 
 def log(*a):
@@ -81,10 +116,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
-    ap.add_argument("--workload", default="sersic64h", choices=["sersic64h", "uneven", "stars32"],
+    ap.add_argument("--workload", default="sersic64h", choices=["sersic64h", "uneven", "stars32", "frames512"],
                     help="uneven: 1,000,000 stamps of side 16-128 (80%% Sersic, 20%% Moffat), "
                          "fused fit vs autotuned work queue; stars32: 1,048,576 32x32 Moffat "
-                         "stars, sizes from weighted moments")
+                         "stars, sizes from weighted moments; frames512: 4,096 512x512 frames, "
+                         "detection and 6 r50 cut-outs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -102,6 +138,8 @@ def main():
         return bench_uneven(args)
     if args.workload == "stars32":
         return bench_stars(args)
+    if args.workload == "frames512":
+        return bench_frames(args)
     forms = [f for f in args.forms.split(",") if f]
     # Stamps are generated (in worker processes) before this process touches
     # the GPU, so no worker is forked from a process with an initialised runtime.
@@ -244,7 +282,9 @@ def main():
                              for f, r in results.items()}},
         "roofline": {"bound": "alu", "kernel": "fit (" + chosen + ")",
                      "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                     "traffic": fit_traffic_bytes() if chosen == "f16" else None,
+                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "launch_ms": round(rc["fit_ms"], 4),
                      "flop_per_pixel_sweep": FLOP_PER_PIXEL_SWEEP,
                      "pixel_sweeps_per_launch": rc["pixel_sweeps"]},
@@ -423,6 +463,94 @@ def bench_stars(args):
                           "max_rel_beta": float(rel[:, 1].max()) if both.any() else None,
                           "max_rel_i0": float(rel[:, 2].max()) if both.any() else None,
                           "within_1e-3": float((rel.max(1) <= 1e-3).mean()) if both.any() else None}
+    print(json.dumps(line), flush=True)
+
+
+def bench_frames(args):
+    """Front end on 512x512 frames: detection (border sky, brightest pixel,
+    growth-curve r50, 6 r50 box), offsets, and the cut into a stamp batch."""
+    import numpy as np
+
+    import synth
+
+    t = time.time()
+    f = synth.make_frames(count=args.count)
+    log("generated %d frames (512x512) in %.1f s" % (f.n, time.time() - t))
+
+    import torch
+
+    import paper_1203_0571_amd as shape
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    fr = shape.DeviceFrames.from_host(f, dev)
+    sigma = torch.from_numpy(f.sigma).to(dev)
+    out = torch.empty(f.n * 128 * 128, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record()
+        d = shape.frame_detect(fr)
+        if ev:
+            ev[1].record()
+        db = shape.frame_cut(fr, d["box"], sigma, out=out)
+        if ev:
+            ev[2].record()
+        return d, db
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        d, db = step(evs[k])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    det_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    cut_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    box = d["box"].cpu().numpy()
+    st = d["status"].cpu().numpy()
+    frame_bytes = float(f.pixels[0].nbytes)
+    # algorithmic bytes of the detection launch: each frame read once, plus
+    # the outputs (info 12 B, peak 8 B, box 12 B, status 4 B)
+    det_bytes = f.n * (frame_bytes + 36.0)
+    achieved = det_bytes / (det_ms * 1e-3) / 1e9
+    cut_px = float((box[:, 2].astype(np.float64) ** 2).sum())
+    log("frames: %.0f frames/s; detect %.3f ms (%.0f GB/s), offsets+cut %.3f ms, %.0f cut px"
+        % (f.n * args.steps / el, det_ms, achieved, cut_ms, cut_px))
+    line = {"metric": "frames processed/sec (512x512 frames: detection + 6 r50 cut-outs)",
+            "value": round(f.n * args.steps / el, 1), "unit": "frames/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(el / args.steps * 1e3, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "frames512: %d x 512x512 frames, one Sersic galaxy each, seed 0"
+                                   % f.n,
+                       "detect_ms": round(det_ms, 4), "offsets_cut_ms": round(cut_ms, 4),
+                       "mean_side": round(float(box[:, 2].mean()), 3),
+                       "nonpositive_flux_frames": int(((st & shape.ST_NONPOSITIVE_FLUX) != 0).sum())},
+            "roofline": {"bound": "hbm", "kernel": "frame detect", "achieved": round(achieved, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "launch_ms": round(det_ms, 4), "bytes_per_launch": det_bytes}}
+    if not args.no_cpu:
+        import oracle
+        m = min(1024, f.n)
+        t = time.perf_counter()
+        ref = [oracle.frame_detect(f.pixels[i].astype(np.float64)) for i in range(m)]
+        cpu_s = time.perf_counter() - t
+        line["cpu_baseline"] = {"value": round(m / cpu_s, 2), "unit": "frames/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": "first %d frames, FP64 oracle detection, one thread, "
+                                          "%.1f s" % (m, cpu_s)}
+        gb = box[:m]
+        gp = d["peak"][:m].cpu().numpy()
+        line["parity"] = {"sample": m,
+                          "box_equal": float(np.mean([tuple(gb[i].tolist()) == ref[i]["box"]
+                                                      for i in range(m)])),
+                          "peak_equal": float(np.mean([tuple(gp[i].tolist()) == ref[i]["peak"]
+                                                       for i in range(m)]))}
     print(json.dumps(line), flush=True)
 
 

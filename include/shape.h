@@ -269,6 +269,54 @@ int shape_queue_graph_create(const shape_batch* batch, const shape_opts* opts,
 int shape_queue_graph_launch(shape_queue_graph* graph, void* stream);
 int shape_queue_graph_destroy(shape_queue_graph* graph);
 
+/* ------------------------------------------------------------------------
+ * Front end on whole frames (Sec. 4.1, the paragraph on the starting point):
+ * find the brightest pixel of each frame, estimate r50 by summing the pixels
+ * outward from it until half the total flux, and cut the square of side
+ * 6 r50 around it into a packed stamp batch for the calls above.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  const void*  pixels;   /* [n][height][width] row-major frames (device); F32, or F16 with scale */
+  const float* scale;    /* [n] F16 dequantisation scale; NULL for F32 */
+  int64_t      n;        /* frames (>= 0) */
+  int32_t      height;   /* 4 .. 4096 */
+  int32_t      width;    /* 4 .. 4096 */
+  int32_t      dtype;    /* shape_dtype */
+  int32_t      reserved;
+} shape_frames;
+
+/*
+ * Per frame: sky = mean of the border pixels; the brightest pixel (first
+ * row-major index among equals); F = sum of (I - sky) over the frame; the
+ * growth curve C(r) = sum of (I - sky) over pixels at distance <= r from the
+ * brightest pixel, r = 1, 2, ..., with C(0) = 0, and r50 its first crossing
+ * of F/2, linearly interpolated (min(H, W)/8 if F <= 0, status
+ * SHAPE_ST_NONPOSITIVE_FLUX); then the square of side round(6 r50), clamped
+ * to [4, min(max_side, H, W)], starting at the peak minus side/2 (integer
+ * division) and shifted to lie inside the frame.  A frame with a NaN or Inf
+ * pixel gets status SHAPE_ST_NONFINITE_INPUT, NaN info, peak (-1, -1) and an
+ * empty box (side 0).
+ *   max_side  in: 4 .. 128
+ *   info  [n][3] out: sky, r50, F       peak [n][2] out: x, y of the brightest pixel
+ *   box   [n][3] out: x0, y0, side      status [n] out
+ * Errors: SHAPE_EINVAL for a NULL or out-of-range argument.
+ */
+int shape_frame_detect(const shape_frames* frames, int32_t max_side, float* info, int32_t* peak,
+                       int32_t* box, uint32_t* status, void* stream);
+
+/* Exclusive prefix sums of side^2 over box [n][3] (device): offset [n] of each
+ * cut-out in the packed stamps, and total [1] = their sum (pixels to
+ * allocate).  n = 0 writes total = 0. */
+int shape_frame_offsets(const int32_t* box, int64_t n, int64_t* offset, int64_t* total,
+                        void* stream);
+
+/* Copy every box of every frame into stamps (FP32, F16 frames dequantised)
+ * at offset[i]; sides [n] (optional, may be NULL) receives each side, so
+ * (stamps, offset, sides) form a shape_batch.  Boxes must lie inside their
+ * frames (as shape_frame_detect makes them); side 0 copies nothing. */
+int shape_frame_cut(const shape_frames* frames, const int32_t* box, const int64_t* offset,
+                    float* stamps, int32_t* sides, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

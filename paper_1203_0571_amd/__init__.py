@@ -89,6 +89,18 @@ class QueueCfg(C.Structure):
     ]
 
 
+class ShapeFrames(C.Structure):
+    _fields_ = [
+        ("pixels", C.c_void_p),
+        ("scale", C.c_void_p),
+        ("n", C.c_int64),
+        ("height", C.c_int32),
+        ("width", C.c_int32),
+        ("dtype", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libshape.so is not built (run __graft_entry__.build() or "
@@ -112,6 +124,12 @@ def _load():
     lib.shape_chi2_bwd.restype = C.c_int
     lib.shape_star_moments.argtypes = [bp, C.c_int32, vp, C.c_double, C.c_int32, vp, vp, vp, vp]
     lib.shape_star_moments.restype = C.c_int
+    fp = C.POINTER(ShapeFrames)
+    lib.shape_frame_detect.argtypes = [fp, C.c_int32, vp, vp, vp, vp, vp]
+    lib.shape_frame_offsets.argtypes = [vp, C.c_int64, vp, vp, vp]
+    lib.shape_frame_cut.argtypes = [fp, vp, vp, vp, vp, vp]
+    for f in ("shape_frame_detect", "shape_frame_offsets", "shape_frame_cut"):
+        getattr(lib, f).restype = C.c_int
     qp = C.POINTER(QueueCfg)
     lib.shape_queue_default_cfg.argtypes = [qp]
     lib.shape_queue_workspace_bytes.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
@@ -209,6 +227,39 @@ class DeviceBatch:
             kw["sides"] = torch.from_numpy(sides).to(dev)
             kw["model"] = torch.from_numpy(batch.model).to(dev)
         return DeviceBatch(**kw)
+
+
+@dataclass
+class DeviceFrames:
+    """Equal frames resident on one GPU: pixels [n, H, W] float32, or float16
+    with a per-frame scale."""
+    pixels: torch.Tensor
+    scale: torch.Tensor | None = None
+
+    @property
+    def n(self):
+        return int(self.pixels.shape[0])
+
+    @property
+    def device(self):
+        return self.pixels.device
+
+    def c_struct(self) -> ShapeFrames:
+        if self.pixels.dim() != 3 or not self.pixels.is_contiguous():
+            raise ValueError("frames must be a contiguous [n, H, W] tensor")
+        f = ShapeFrames()
+        f.pixels = _ptr(self.pixels)
+        f.scale = _ptr(self.scale)
+        f.n = self.n
+        f.height = int(self.pixels.shape[1])
+        f.width = int(self.pixels.shape[2])
+        f.dtype = F16_SCALED if self.pixels.dtype == torch.float16 else F32
+        return f
+
+    @staticmethod
+    def from_host(frames, device="cuda"):
+        """Upload a synth.Frames (numpy) to the GPU."""
+        return DeviceFrames(pixels=torch.from_numpy(frames.pixels).to(torch.device(device)))
 
 
 def _outs(n, device, *shapes_dtypes):
@@ -310,6 +361,49 @@ class SersicChi2(torch.autograd.Function):
 
 def sersic_chi2(params: torch.Tensor, batch: DeviceBatch) -> torch.Tensor:
     return SersicChi2.apply(params, batch)
+
+
+def frame_detect(frames: DeviceFrames, max_side: int = 128):
+    """shape_frame_detect: dict(info [n,3] = sky, r50, F; peak [n,2]; box [n,3]; status)."""
+    n, dev = frames.n, frames.device
+    info, peak, box, st = _outs(n, dev, ((n, 3), torch.float32), ((n, 2), torch.int32),
+                                ((n, 3), torch.int32), ((n,), torch.int32))
+    f = frames.c_struct()
+    _check(lib.shape_frame_detect(C.byref(f), int(max_side), _ptr(info), _ptr(peak), _ptr(box),
+                                  _ptr(st), _stream(dev)), "shape_frame_detect")
+    return dict(info=info, peak=peak, box=box, status=st)
+
+
+def frame_offsets(box: torch.Tensor):
+    """shape_frame_offsets: (offset [n] int64, total [1] int64), on the device."""
+    n, dev = int(box.shape[0]), box.device
+    off, tot = _outs(n, dev, ((n,), torch.int64), ((1,), torch.int64))
+    _check(lib.shape_frame_offsets(_ptr(box), n, _ptr(off), _ptr(tot), _stream(dev)),
+           "shape_frame_offsets")
+    return off, tot
+
+
+def frame_cut(frames: DeviceFrames, box: torch.Tensor, sigma: torch.Tensor,
+              out: torch.Tensor | None = None) -> DeviceBatch:
+    """Cut the boxes out into a DeviceBatch (FP32 stamps); sigma [n] is each
+    frame's pixel noise.  Without `out` the total pixel count is read back to
+    size the stamps; with `out` (float32, at least n * max_side^2 elements)
+    nothing is read back and the batch views all of `out`."""
+    n, dev = frames.n, frames.device
+    off, tot = frame_offsets(box)
+    if out is None:
+        total = int(tot.item())
+        stamps = torch.empty(max(total, 1), dtype=torch.float32, device=dev)
+    else:
+        if out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor")
+        stamps, total = out, out.numel()
+    sides = torch.empty(n, dtype=torch.int32, device=dev)
+    f = frames.c_struct()
+    _check(lib.shape_frame_cut(C.byref(f), _ptr(box), _ptr(off), _ptr(stamps), _ptr(sides),
+                               _stream(dev)), "shape_frame_cut")
+    return DeviceBatch(pixels=stamps[:total] if total else stamps[:0], sigma=sigma, offsets=off,
+                       sides=sides)
 
 
 STAR_GAUSSIAN = 0

@@ -3,9 +3,11 @@
 //
 // With r_i = (d_i - m_i) / sigma the adjoint of pixel i is
 //   dL/dm_i = -(2 / sigma) r_i dL/dchi2,
-// and dL/dp_k = sum_i dL/dm_i dm_i/dp_k.  The backward sweep is the same
-// device function the fit uses for its J^T r and J^T J, so the normal
-// equations it can also return are exactly the LM's.
+// and dL/dp_k = sum_i dL/dm_i dm_i/dp_k.  The backward sweep is the device
+// function the fit uses for its J^T r and J^T J, instantiated in FP64 (FP64
+// render, Jacobian and sums; log2 / exp2 from series): the FP32 instance's
+// rounding of the exponent b t is amplified where the gradient components
+// cancel over the stamp, up to ~1e-4 of the largest component.
 #include "kernels.hpp"
 #include "sweep.hpp"
 
@@ -45,9 +47,9 @@ __global__ __launch_bounds__(kWave) void chi2_kernel(shape_batch b, const float*
       continue;
     }
     {
-      Acc<EM> acc;
-      sweep<DT, MODEL, EM>(b, st, make_trial(p, MODEL, p[5]), acc);
-      reduce_store<EM>(acc, S, lane);
+      Acc<EM, double> acc;
+      sweep<DT, MODEL, EM, kWave, double>(b, st, make_trial<double>(p, MODEL, p[5]), acc);
+      reduce_store<EM, double>(acc, S, lane);
     }
     // lane 0 wrote S and is the only reader
     const double inv2 = 1.0 / (st.sigma * st.sigma);

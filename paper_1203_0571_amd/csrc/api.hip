@@ -181,6 +181,39 @@ int shape_star_moments(const shape_batch* b, int32_t profile, const float* rec, 
       launch_stars(*b, profile, rec, tol, max_iter, out, iters, status, (hipStream_t)stream));
 }
 
+static int check_frames(const shape_frames* f) {
+  if (!f || f->n < 0 || f->height < 4 || f->height > 4096 || f->width < 4 || f->width > 4096)
+    return SHAPE_EINVAL;
+  if (f->dtype != SHAPE_F32 && f->dtype != SHAPE_F16_SCALED) return SHAPE_EINVAL;
+  if (f->n > 0 && (!f->pixels || (f->dtype == SHAPE_F16_SCALED && !f->scale))) return SHAPE_EINVAL;
+  return SHAPE_OK;
+}
+
+int shape_frame_detect(const shape_frames* f, int32_t max_side, float* info, int32_t* peak,
+                       int32_t* box, uint32_t* status, void* stream) {
+  int rc = check_frames(f);
+  if (rc != SHAPE_OK) return rc;
+  if (max_side < 4 || max_side > 128) return SHAPE_EINVAL;
+  if (f->n == 0) return SHAPE_OK;
+  if (!info || !peak || !box || !status) return SHAPE_EINVAL;
+  return from_hip(launch_frame_detect(*f, max_side, info, peak, box, status, (hipStream_t)stream));
+}
+
+int shape_frame_offsets(const int32_t* box, int64_t n, int64_t* offset, int64_t* total,
+                        void* stream) {
+  if (n < 0 || !total || (n > 0 && (!box || !offset))) return SHAPE_EINVAL;
+  return from_hip(launch_frame_offsets(box, n, offset, total, (hipStream_t)stream));
+}
+
+int shape_frame_cut(const shape_frames* f, const int32_t* box, const int64_t* offset,
+                    float* stamps, int32_t* sides, void* stream) {
+  int rc = check_frames(f);
+  if (rc != SHAPE_OK) return rc;
+  if (f->n == 0) return SHAPE_OK;
+  if (!box || !offset || !stamps) return SHAPE_EINVAL;
+  return from_hip(launch_frame_cut(*f, box, offset, stamps, sides, (hipStream_t)stream));
+}
+
 int shape_queue_default_cfg(shape_queue_cfg* c) {
   if (!c) return SHAPE_EINVAL;
   c->team = 1;

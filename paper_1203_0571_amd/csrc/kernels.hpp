@@ -35,6 +35,14 @@ hipError_t launch_stars(const shape_batch& b, int profile, const float* rec, dou
                         int max_iter, float* out, int32_t* iters, uint32_t* status,
                         hipStream_t stream);
 
+int frame_bins(int height, int width);
+hipError_t launch_frame_detect(const shape_frames& f, int max_side, float* info, int32_t* peak,
+                               int32_t* box, uint32_t* status, hipStream_t stream);
+hipError_t launch_frame_offsets(const int32_t* box, int64_t n, int64_t* offset, int64_t* total,
+                                hipStream_t stream);
+hipError_t launch_frame_cut(const shape_frames& f, const int32_t* box, const int64_t* offset,
+                            float* stamps, int32_t* sides, hipStream_t stream);
+
 hipError_t launch_chi2(const shape_batch& b, const float* params, const float* grad_chi2,
                        float* chi2, float* grad_p, float* jtj, float* jtr, bool grad,
                        hipStream_t stream);

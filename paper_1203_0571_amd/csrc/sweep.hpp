@@ -29,122 +29,180 @@ __host__ __device__ inline constexpr int nth_bit(uint32_t m, int a) {
   return 0;
 }
 
-// Trial parameters as the FP32 sweep uses them.
-struct TrialF {
-  float x0, y0, e1, e2, a11, a12, a22, invD;
-  float I0, sky;
-  // Sersic: t = 2^(L ha + hc), m0 = 2^(nb2 t); Moffat: base = 1 + R^2 irdsq
-  float ha, hc, nb2, b, hinvn, invnRe, ndb, invn2, nlnRe;
-  float beta, irdsq, twoirdsq_rd;
+// FP64 log2 and exp2 for the FP64 instance of the sweep, from series.
+//   log2 x: x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh z,
+//           z = (m - 1)/(m + 1), |z| <= 3 - 2 sqrt(2); the odd series to z^23
+//           leaves a relative error below 1e-19.
+//   exp2 x: x = k + f with k = rint(x), |f| <= 1/2; e^(f ln 2) by its Taylor
+//           series to degree 13 (remainder below 1e-17), scaled by 2^k.
+__device__ __forceinline__ double log2_f64(double x) {
+  int e;
+  double m = __builtin_frexp(x, &e);  // [0.5, 1)
+  if (m < 0.70710678118654752) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double z = (m - 1.0) / (m + 1.0);
+  const double w = z * z;
+  double s = 1.0 / 23.0;
+#pragma unroll
+  for (int k = 21; k >= 1; k -= 2) s = fma(s, w, 1.0 / (double)k);
+  return (double)e + 2.0 * z * s * kLog2e;
+}
+
+__device__ __forceinline__ double exp2_f64(double x) {
+  if (!(x > -1100.0)) return x != x ? x : 0.0;
+  if (x > 1100.0) return __builtin_inf();
+  const double k = __builtin_rint(x);
+  const double y = (x - k) * kLn2;
+  double s = 1.0;
+#pragma unroll
+  for (int n = 13; n >= 1; --n) s = fma(s, y / (double)n, 1.0);
+  return __builtin_ldexp(s, (int)k);
+}
+
+// Arithmetic of one sweep instance: FP32 with the hardware transcendentals
+// (about 1 ulp; the fit), or FP64 with the series above (the chi^2 gradient).
+template <typename T>
+struct Arith;
+template <>
+struct Arith<float> {
+  static __device__ __forceinline__ float ex2(float x) { return fast_exp2(x); }
+  static __device__ __forceinline__ float lg2(float x) { return fast_log2(x); }
+  static __device__ __forceinline__ float rcp(float x) { return fast_rcp(x); }
+  static __device__ __forceinline__ float fma(float a, float b, float c) { return fmaf(a, b, c); }
+  static __device__ __forceinline__ float uni(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+  }
+  static constexpr float kR2Floor = kR2Min;
+};
+template <>
+struct Arith<double> {
+  static __device__ __forceinline__ double ex2(double x) { return exp2_f64(x); }
+  static __device__ __forceinline__ double lg2(double x) { return log2_f64(x); }
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double fma(double a, double b, double c) { return ::fma(a, b, c); }
+  static __device__ __forceinline__ double uni(double v) { return v; }
+  static constexpr double kR2Floor = 1e-8;
 };
 
-template <uint32_t EM>
+// Trial parameters as a sweep instance uses them.
+template <typename T>
+struct Trial {
+  T x0, y0, e1, e2, a11, a12, a22, invD;
+  T I0, sky;
+  // Sersic: t = 2^(L ha + hc), m0 = 2^(nb2 t); Moffat: base = 1 + R^2 irdsq
+  T ha, hc, nb2, b, hinvn, invnRe, ndb, invn2, nlnRe;
+  T beta, irdsq, twoirdsq_rd;
+};
+using TrialF = Trial<float>;
+
+template <uint32_t EM, typename T = float>
 struct Acc {
   double c2;
   double g[8];
-  float A[36];
+  T A[36];
 };
 
-__device__ __forceinline__ float uniform(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
-}
-
-__device__ __forceinline__ TrialF make_trial(const double* p, int model, double beta) {
-  // The sweep is FP32, so its constants are formed in FP32 from the FP64
-  // parameters (hardware log2 / rcp, about 1 ulp).
-  TrialF t;
-  const float e1 = (float)p[2], e2 = (float)p[3];
-  t.x0 = uniform((float)p[0]);
-  t.y0 = uniform((float)p[1]);
-  t.e1 = uniform(e1);
-  t.e2 = uniform(e2);
-  t.a11 = uniform(1.0f - e1);
-  t.a12 = uniform(-e2);
-  t.a22 = uniform(1.0f + e1);
-  t.invD = uniform(fast_rcp((float)(1.0 - p[2] * p[2] - p[3] * p[3])));
-  t.I0 = uniform((float)p[6]);
-  t.sky = uniform((float)p[7]);
+// The sweep's constants from the FP64 parameters, formed in the instance's
+// own arithmetic (FP32: hardware log2 / rcp, about 1 ulp).
+template <typename T = float>
+__device__ __forceinline__ Trial<T> make_trial(const double* p, int model, double beta) {
+  using A = Arith<T>;
+  Trial<T> t;
+  const T e1 = (T)p[2], e2 = (T)p[3];
+  t.x0 = A::uni((T)p[0]);
+  t.y0 = A::uni((T)p[1]);
+  t.e1 = A::uni(e1);
+  t.e2 = A::uni(e2);
+  t.a11 = A::uni((T)1 - e1);
+  t.a12 = A::uni(-e2);
+  t.a22 = A::uni((T)1 + e1);
+  t.invD = A::uni(A::rcp((T)(1.0 - p[2] * p[2] - p[3] * p[3])));
+  t.I0 = A::uni((T)p[6]);
+  t.sky = A::uni((T)p[7]);
   if (model == SHAPE_SERSIC) {
-    const float n = (float)p[5], Re = (float)p[4];
-    const float invn = fast_rcp(n), l2Re = fast_log2(Re);
+    const T n = (T)p[5], Re = (T)p[4];
+    const T invn = A::rcp(n), l2Re = A::lg2(Re);
     double b, db;
     sersic_bn(p[5], &b, &db);
-    t.ha = uniform(0.5f * invn);
-    t.hc = uniform(-l2Re * invn);
-    t.nb2 = uniform((float)(-b * kLog2e));
-    t.b = uniform((float)b);
-    t.hinvn = uniform(0.5f * invn);
-    t.invnRe = uniform(invn * fast_rcp(Re));
-    t.ndb = uniform((float)(-db));
-    t.invn2 = uniform(invn * invn);
-    t.nlnRe = uniform(-(float)kLn2 * l2Re);
+    t.ha = A::uni((T)0.5 * invn);
+    t.hc = A::uni(-l2Re * invn);
+    t.nb2 = A::uni((T)(-b * kLog2e));
+    t.b = A::uni((T)b);
+    t.hinvn = A::uni((T)0.5 * invn);
+    t.invnRe = A::uni(invn * A::rcp(Re));
+    t.ndb = A::uni((T)(-db));
+    t.invn2 = A::uni(invn * invn);
+    t.nlnRe = A::uni(-(T)kLn2 * l2Re);
   } else {
-    const float rd = (float)p[4];
-    const float ird = fast_rcp(rd);
-    t.beta = uniform((float)beta);
-    t.irdsq = uniform(ird * ird);
-    t.twoirdsq_rd = uniform(2.0f * ird * ird * ird);
+    const T rd = (T)p[4];
+    const T ird = A::rcp(rd);
+    t.beta = A::uni((T)beta);
+    t.irdsq = A::uni(ird * ird);
+    t.twoirdsq_rd = A::uni((T)2 * ird * ird * ird);
   }
   return t;
 }
 
 // One sweep: model, residual, Jacobian columns in EM, and their sums.
-template <int DT, int MODEL, uint32_t EM, int STRIDE = kWave>
-__device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, const TrialF& t,
-                             Acc<EM>& acc, int tid = -1) {
+template <int DT, int MODEL, uint32_t EM, int STRIDE = kWave, typename T = float>
+__device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, const Trial<T>& t,
+                             Acc<EM, T>& acc, int tid = -1) {
+  using A = Arith<T>;
   acc.c2 = 0.0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) acc.g[k] = 0.0;
 #pragma unroll
-  for (int k = 0; k < 36; ++k) acc.A[k] = 0.0f;
+  for (int k = 0; k < 36; ++k) acc.A[k] = (T)0;
   for_pixels<STRIDE>(st.side, [&](int k, int i, int j) {
-    const float d = load_px<DT>(b.pixels, st.off, k, st.scale);
-    const float u1 = (float)j - t.x0, u2 = (float)i - t.y0;
-    const float v1 = fmaf(t.a11, u1, t.a12 * u2);
-    const float v2 = fmaf(t.a12, u1, t.a22 * u2);
-    const float q = fmaf(v1, v1, v2 * v2);
-    float R2 = q * t.invD;
-    const bool floored = R2 < kR2Min;
-    R2 = floored ? kR2Min : R2;
-    float J[8];
-    float m0, dmdR2;
+    const T d = (T)load_px<DT>(b.pixels, st.off, k, st.scale);
+    const T u1 = (T)j - t.x0, u2 = (T)i - t.y0;
+    const T v1 = A::fma(t.a11, u1, t.a12 * u2);
+    const T v2 = A::fma(t.a12, u1, t.a22 * u2);
+    const T q = A::fma(v1, v1, v2 * v2);
+    T R2 = q * t.invD;
+    const bool floored = R2 < A::kR2Floor;
+    R2 = floored ? A::kR2Floor : R2;
+    T J[8];
+    T m0, dmdR2;
     if constexpr (MODEL == SHAPE_SERSIC) {
-      const float L = fast_log2(R2);
-      const float tt = fast_exp2(fmaf(L, t.ha, t.hc));
-      m0 = fast_exp2(t.nb2 * tt);
-      const float w = t.I0 * m0;
-      const float ct = w * t.b * tt;
-      dmdR2 = -ct * fast_rcp(R2) * t.hinvn;
+      const T L = A::lg2(R2);
+      const T tt = A::ex2(A::fma(L, t.ha, t.hc));
+      m0 = A::ex2(t.nb2 * tt);
+      const T w = t.I0 * m0;
+      const T ct = w * t.b * tt;
+      dmdR2 = -ct * A::rcp(R2) * t.hinvn;
       if constexpr (has(EM, 4)) J[4] = ct * t.invnRe;
       if constexpr (has(EM, 5)) {
-        const float lns = fmaf(L, (float)(0.5 * kLn2), t.nlnRe);
-        J[5] = fmaf(w * tt, t.ndb, ct * lns * t.invn2);
+        const T lns = A::fma(L, (T)(0.5 * kLn2), t.nlnRe);
+        J[5] = A::fma(w * tt, t.ndb, ct * lns * t.invn2);
       }
     } else {
-      const float base = fmaf(R2, t.irdsq, 1.0f);
-      const float lb = fast_log2(base);
-      m0 = fast_exp2(-t.beta * lb);
-      const float w = t.I0 * m0;
-      const float gb = w * t.beta * fast_rcp(base);
+      const T base = A::fma(R2, t.irdsq, (T)1);
+      const T lb = A::lg2(base);
+      m0 = A::ex2(-t.beta * lb);
+      const T w = t.I0 * m0;
+      const T gb = w * t.beta * A::rcp(base);
       dmdR2 = -gb * t.irdsq;
       if constexpr (has(EM, 4)) J[4] = gb * R2 * t.twoirdsq_rd;
-      if constexpr (has(EM, 5)) J[5] = -w * lb * (float)kLn2;   // d/dbeta
+      if constexpr (has(EM, 5)) J[5] = -w * lb * (T)kLn2;   // d/dbeta
     }
-    dmdR2 = floored ? 0.0f : dmdR2;
-    const float r = d - fmaf(t.I0, m0, t.sky);
+    dmdR2 = floored ? (T)0 : dmdR2;
+    const T r = d - A::fma(t.I0, m0, t.sky);
     if constexpr (has(EM, 0) || has(EM, 1)) {
-      const float g2 = dmdR2 * (-2.0f * t.invD);
-      J[0] = g2 * fmaf(t.a11, v1, t.a12 * v2);
-      J[1] = g2 * fmaf(t.a12, v1, t.a22 * v2);
+      const T g2 = dmdR2 * ((T)-2 * t.invD);
+      J[0] = g2 * A::fma(t.a11, v1, t.a12 * v2);
+      J[1] = g2 * A::fma(t.a12, v1, t.a22 * v2);
     }
     if constexpr (has(EM, 2) || has(EM, 3)) {
-      const float ti = 2.0f * t.invD;
-      const float qq = q * ti * t.invD;
-      J[2] = dmdR2 * fmaf(ti, fmaf(v2, u2, -v1 * u1), t.e1 * qq);
-      J[3] = dmdR2 * fmaf(ti, -fmaf(v1, u2, v2 * u1), t.e2 * qq);
+      const T ti = (T)2 * t.invD;
+      const T qq = q * ti * t.invD;
+      J[2] = dmdR2 * A::fma(ti, A::fma(v2, u2, -v1 * u1), t.e1 * qq);
+      J[3] = dmdR2 * A::fma(ti, -A::fma(v1, u2, v2 * u1), t.e2 * qq);
     }
     J[6] = m0;
-    J[7] = 1.0f;
+    J[7] = (T)1;
     const double rd = (double)r;
     acc.c2 = fma(rd, rd, acc.c2);
 #pragma unroll
@@ -157,7 +215,7 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
         if (c == 7)
           acc.A[tri(a, c)] += J[a];
         else
-          acc.A[tri(a, c)] = fmaf(J[a], J[c], acc.A[tri(a, c)]);
+          acc.A[tri(a, c)] = A::fma(J[a], J[c], acc.A[tri(a, c)]);
       }
     }
   }, tid);
@@ -167,8 +225,8 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
 // them (FP64) at dst: [0] = chi^2 sum, [1 + k] = (J^T r)_k, [9 + tri] = J^T J.
 // One quantity at a time, with scheduling barriers, so the reductions do not
 // all hold registers at once.
-template <uint32_t EM>
-__device__ __forceinline__ void reduce_store(const Acc<EM>& acc, double* dst, int lane) {
+template <uint32_t EM, typename T = float>
+__device__ __forceinline__ void reduce_store(const Acc<EM, T>& acc, double* dst, int lane) {
   {
     const double v = wave_sum(acc.c2);
     if (lane == 0) dst[0] = v;
@@ -186,7 +244,7 @@ __device__ __forceinline__ void reduce_store(const Acc<EM>& acc, double* dst, in
 #pragma unroll
     for (int c = a; c < 8; ++c) {
       if (has(EM, a) && has(EM, c)) {
-        const float v = wave_sum(acc.A[tri(a, c)]);
+        const T v = wave_sum(acc.A[tri(a, c)]);
         if (lane == 0) dst[9 + tri(a, c)] = (double)v;
       } else if (lane == 0) {
         dst[9 + tri(a, c)] = 0.0;

@@ -179,3 +179,41 @@ def test_star_moments_argument_errors(shape):
     assert L.shape_star_moments(None, 1, out, 1e-4, 20, out, out, out, None) == shape.EINVAL
     e = _batch(shape, n=0, pixels=None, sigma=None)
     assert L.shape_star_moments(C.byref(e), 0, None, 1e-4, 20, None, None, None, None) == shape.OK
+
+
+def _frames(shape, **kw):
+    f = shape.ShapeFrames()
+    f.pixels = 0x1000
+    f.scale = None
+    f.n = 3
+    f.height = 64
+    f.width = 80
+    f.dtype = shape.F32
+    for k, v in kw.items():
+        setattr(f, k, v)
+    return f
+
+
+def test_frame_argument_errors(shape):
+    L = shape.lib
+    out = C.c_void_p(0x3000)
+    assert C.sizeof(shape.ShapeFrames) == 2 * 8 + 8 + 4 * 4
+    for bad in [dict(n=-1), dict(height=3), dict(width=4097), dict(dtype=7), dict(pixels=None),
+                dict(dtype=shape.F16_SCALED)]:
+        f = _frames(shape, **bad)
+        assert L.shape_frame_detect(C.byref(f), 128, out, out, out, out, None) == shape.EINVAL
+        assert L.shape_frame_cut(C.byref(f), out, out, out, None, None) == shape.EINVAL
+    f = _frames(shape)
+    assert L.shape_frame_detect(None, 128, out, out, out, out, None) == shape.EINVAL
+    for ms in (3, 129):
+        assert L.shape_frame_detect(C.byref(f), ms, out, out, out, out, None) == shape.EINVAL
+    assert L.shape_frame_detect(C.byref(f), 128, None, out, out, out, None) == shape.EINVAL
+    assert L.shape_frame_detect(C.byref(f), 128, out, out, None, out, None) == shape.EINVAL
+    assert L.shape_frame_cut(C.byref(f), None, out, out, None, None) == shape.EINVAL
+    assert L.shape_frame_cut(C.byref(f), out, out, None, None, None) == shape.EINVAL
+    assert L.shape_frame_offsets(out, -1, out, out, None) == shape.EINVAL
+    assert L.shape_frame_offsets(out, 3, out, None, None) == shape.EINVAL
+    assert L.shape_frame_offsets(None, 3, out, out, None) == shape.EINVAL
+    e = _frames(shape, n=0, pixels=None)
+    assert L.shape_frame_detect(C.byref(e), 128, None, None, None, None, None) == shape.OK
+    assert L.shape_frame_cut(C.byref(e), None, None, None, None, None) == shape.OK

@@ -231,10 +231,11 @@ int shape_star_moments(const shape_batch* batch, int32_t profile, const float* r
  *   shape_queue_finish  writes the same outputs as shape_fit_sersic.
  * A step can be captured once into a hipGraph and replayed
  * (shape_queue_graph_*).  The caller owns the workspace (device memory of
- * shape_queue_workspace_bytes(n) bytes); its first 16 bytes are four uint32
- * (next_big, next_small, active, n_team): `active` counts the stamps still
- * iterating after the last step and is valid once the stream has
- * synchronised.  Steps on one workspace must not overlap.
+ * shape_queue_workspace_bytes(n) bytes); the uint32 at byte offset 8,
+ * `active`, counts the stamps still iterating after the last step and is
+ * valid once the stream has synchronised.  A step is one persistent launch
+ * per model present (Sersic, and Moffat when the batch has a model array).
+ * Steps on one workspace must not overlap.
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t team;           /* waves per stamp for stamps with side >= team_min_side: 1, 2, 4 */

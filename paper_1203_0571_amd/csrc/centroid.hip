@@ -18,7 +18,7 @@ __device__ inline int ring_of(int d2) {
   return r;
 }
 
-template <int DT>
+template <int DT, int SIDE>
 __global__ __launch_bounds__(kWave) void centroid_kernel(shape_batch b, KOpts o, float* rec,
                                                          int32_t* iters, uint32_t* status) {
   // Growth curve: ring sums in fixed point, so the atomics are exact and the
@@ -36,7 +36,10 @@ __global__ __launch_bounds__(kWave) void centroid_kernel(shape_batch b, KOpts o,
       }
       continue;
     }
-    const int W = st.side;
+    const int W = SIDE ? SIDE : st.side;
+    // Passes 1 and 2 read the stamp from memory; the iterations of pass 3
+    // sweep it from registers when the batch's side allows (StampPixels).
+    const StampPixels<DT, 0> mem(b, st, lane);
 
     // Pass 1: finiteness, border sum, brightest pixel, largest |I|.
     double border = 0.0;
@@ -44,8 +47,7 @@ __global__ __launch_bounds__(kWave) void centroid_kernel(shape_batch b, KOpts o,
     int besti = 0x7fffffff;
     float amax = 0.0f;
     bool nonfinite = false;
-    for_pixels(W, [&](int k, int i, int j) {
-      float v = load_px<DT>(b.pixels, st.off, k, st.scale);
+    mem.each([&](float v, int k, int i, int j) {
       nonfinite |= !__builtin_isfinite(v);
       if (i == 0 || j == 0 || i == W - 1 || j == W - 1) border += (double)v;
       if (v > best) {  // k increases, so ties keep the lowest index
@@ -83,8 +85,8 @@ __global__ __launch_bounds__(kWave) void centroid_kernel(shape_batch b, KOpts o,
     const double fix = exp2(floor(log2(2.3e18 / ((double)st.npix * fmaxabs))));
     for (int r = lane; r < nrings; r += kWave) ring[r] = 0ull;
     __syncthreads();
-    for_pixels(W, [&](int k, int i, int j) {
-      double f = (double)load_px<DT>(b.pixels, st.off, k, st.scale) - sky0;
+    mem.each([&](float v, int, int i, int j) {
+      double f = (double)v - sky0;
       int d2 = (i - i0) * (i - i0) + (j - j0) * (j - j0);
       long long q = __double2ll_rn(f * fix);
       atomicAdd(&ring[ring_of(d2)], (unsigned long long)q);
@@ -92,11 +94,13 @@ __global__ __launch_bounds__(kWave) void centroid_kernel(shape_batch b, KOpts o,
     __syncthreads();
     // Every lane scans the rings (LDS broadcast reads) and reaches the same r50.
     long long F = 0;
+#pragma unroll 1
     for (int r = 0; r < nrings; ++r) F += (long long)ring[r];
     uint32_t stt = 0;
     double r50 = 0.125 * W;
     if (F > 0) {
       long long cum = (long long)ring[0], prev = 0;
+#pragma unroll 1
       for (int r = 1; r < nrings; ++r) {
         cum += (long long)ring[r];
         if (2 * cum >= F) {  // first crossing of half the total flux
@@ -113,6 +117,7 @@ __global__ __launch_bounds__(kWave) void centroid_kernel(shape_batch b, KOpts o,
     sigw = fmin(fmax(sigw, 1.0), 0.25 * W);
 
     // Pass 3: centroid iteration from the brightest pixel.
+    const StampPixels<DT, SIDE> px(b, st, lane);
     double x = j0, y = i0;
     const float c2 = (float)(kLog2e / (2.0 * sigw * sigw));
     const float skyf = (float)sky0;
@@ -120,8 +125,7 @@ __global__ __launch_bounds__(kWave) void centroid_kernel(shape_batch b, KOpts o,
     while (it < o.max_iter_centroid) {
       double N = 0.0, Sx = 0.0, Sy = 0.0;
       const float xf = (float)x, yf = (float)y;
-      for_pixels(W, [&](int k, int i, int j) {
-        float v = load_px<DT>(b.pixels, st.off, k, st.scale);
+      px.each([&](float v, int, int i, int j) {
         float t1 = (float)j - xf, t2 = (float)i - yf;
         float w = fast_exp2(-(t1 * t1 + t2 * t2) * c2);
         float fw = (v - skyf) * w;
@@ -166,17 +170,30 @@ __global__ __launch_bounds__(kWave) void centroid_kernel(shape_batch b, KOpts o,
   }
 }
 
+template <int DT>
+void launch_side(int side, int64_t grid, const shape_batch& b, const KOpts& o, float* rec,
+                 int32_t* iters, uint32_t* status, hipStream_t stream) {
+  const dim3 g((unsigned)grid), t(kWave);
+  switch (side) {
+    case 8: hipLaunchKernelGGL((centroid_kernel<DT, 8>), g, t, 0, stream, b, o, rec, iters, status); break;
+    case 16: hipLaunchKernelGGL((centroid_kernel<DT, 16>), g, t, 0, stream, b, o, rec, iters, status); break;
+    case 32: hipLaunchKernelGGL((centroid_kernel<DT, 32>), g, t, 0, stream, b, o, rec, iters, status); break;
+    case 64: hipLaunchKernelGGL((centroid_kernel<DT, 64>), g, t, 0, stream, b, o, rec, iters, status); break;
+    default: hipLaunchKernelGGL((centroid_kernel<DT, 0>), g, t, 0, stream, b, o, rec, iters, status);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_centroid(const shape_batch& b, const KOpts& o, float* rec, int32_t* iters,
                            uint32_t* status, hipStream_t stream) {
   const int64_t grid = b.n < (1ll << 30) ? b.n : (1ll << 30);
+  // A batch of one side that divides 64 keeps each stamp in registers.
+  const int side = (!b.side && register_side(b.side0)) ? b.side0 : 0;
   if (b.dtype == SHAPE_F32)
-    hipLaunchKernelGGL(centroid_kernel<SHAPE_F32>, dim3((unsigned)grid), dim3(kWave), 0, stream, b,
-                       o, rec, iters, status);
+    launch_side<SHAPE_F32>(side, grid, b, o, rec, iters, status, stream);
   else
-    hipLaunchKernelGGL(centroid_kernel<SHAPE_F16_SCALED>, dim3((unsigned)grid), dim3(kWave), 0,
-                       stream, b, o, rec, iters, status);
+    launch_side<SHAPE_F16_SCALED>(side, grid, b, o, rec, iters, status, stream);
   return hipGetLastError();
 }
 

@@ -128,6 +128,72 @@ __device__ inline void for_pixels(int side, F&& f, int tid = -1) {
   }
 }
 
+// Stamp pixel at a 32-bit element index from the stamp's own base.
+template <int DT>
+__device__ __forceinline__ float load_rel(const void* sp, uint32_t k, float scale) {
+  if constexpr (DT == SHAPE_F32) {
+    return static_cast<const float*>(sp)[k];
+  } else {
+    return static_cast<float>(static_cast<const _Float16*>(sp)[k]) * scale;
+  }
+}
+
+template <int DT>
+__device__ __forceinline__ const void* stamp_base(const shape_batch& b, const Stamp& st) {
+  if constexpr (DT == SHAPE_F32)
+    return static_cast<const float*>(b.pixels) + st.off;
+  else
+    return static_cast<const _Float16*>(b.pixels) + st.off;
+}
+
+// The pixels of one stamp as a wave sweeps them, for kernels that sweep a
+// stamp several times: each(f) calls f(value, k, i, j) for every pixel k of
+// this lane (row i, column j).  SIDE = 0: any side, read from memory on every
+// sweep.  SIDE in {8, 16, 32, 64}: the stamp is read once into registers,
+// lane l holding pixel l + 64 m in slot m (row m * 64 / SIDE + l / SIDE,
+// column l % SIDE), and every later sweep runs from registers.
+template <int DT, int SIDE>
+struct StampPixels {
+  static_assert(SIDE == 8 || SIDE == 16 || SIDE == 32 || SIDE == 64, "side must divide 64");
+  static constexpr int kSlots = SIDE * SIDE / kWave;
+  float v[kSlots];
+  int lane;
+  __device__ __forceinline__ StampPixels(const shape_batch& b, const Stamp& st, int l) : lane(l) {
+    const void* sp = stamp_base<DT>(b, st);
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m) v[m] = load_rel<DT>(sp, (uint32_t)(l + kWave * m), st.scale);
+  }
+  template <class F>
+  __device__ __forceinline__ void each(F&& f) const {
+    int il = lane / SIDE, jl = lane & (SIDE - 1);
+    // Opaque to the optimiser, so coordinates derived from il, jl are formed
+    // anew in each sweep instead of being hoisted out of the caller's
+    // iteration loop into one register per pixel.
+    asm volatile("" : "+v"(il), "+v"(jl));
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m) f(v[m], lane + kWave * m, m * (kWave / SIDE) + il, jl);
+  }
+};
+
+template <int DT>
+struct StampPixels<DT, 0> {
+  const void* base;
+  int64_t off;
+  int side;
+  float scale;
+  __device__ __forceinline__ StampPixels(const shape_batch& b, const Stamp& st, int)
+      : base(b.pixels), off(st.off), side(st.side), scale(st.scale) {}
+  template <class F>
+  __device__ __forceinline__ void each(F&& f) const {
+    for_pixels(side, [&](int k, int i, int j) { f(load_px<DT>(base, off, k, scale), k, i, j); });
+  }
+};
+
+// Whether a batch of one side (no side array) may use StampPixels<_, side0>.
+__host__ __device__ inline constexpr bool register_side(int side) {
+  return side == 8 || side == 16 || side == 32 || side == 64;
+}
+
 // Make LDS writes of one lane visible to the other lanes of its wave (no
 // cross-wave barrier: usable where the waves of a workgroup diverge).
 __device__ inline void wave_sync() {

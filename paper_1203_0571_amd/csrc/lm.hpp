@@ -114,11 +114,11 @@ __device__ __forceinline__ void team_sync() {
 // One sweep at trial t; the team's reduced sums are left in S (LDS, kSums
 // doubles).  xs is LDS scratch of TEAM * kSums doubles for the cross-wave
 // combination (unused for TEAM == 1).  tid = thread index within the team.
-template <int DT, int MODEL, uint32_t EM, int TEAM>
+template <int DT, int MODEL, uint32_t EM, int TEAM, int LAYOUT = kLayoutAny>
 __device__ __forceinline__ void sweep_sums(const shape_batch& b, const Stamp& st, const TrialF& t,
                                   double* S, double* xs, int tid) {
   Acc<EM> acc;
-  sweep<DT, MODEL, EM, kWave * TEAM>(b, st, t, acc, tid);
+  sweep<DT, MODEL, EM, kWave * TEAM, float, LAYOUT>(b, st, t, acc, tid);
   const int lane = tid & (kWave - 1);
   double* dst = (TEAM == 1) ? S : xs + (tid / kWave) * kSums;
   team_sync<TEAM>();  // previous readers of S / xs are done
@@ -188,7 +188,7 @@ __device__ __forceinline__ AmpStep profile_amplitudes(double* S, double I0, int 
 // Starting point: p from p_init or the moments record, the amplitude optimum
 // at that shape (Sec. 4.1) and the first sweep, whose profiled sums become the
 // current point (W.sums[W.cur]).  The state ends in W.L.
-template <int DT, int MODEL, uint32_t MASK, int TEAM>
+template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT = kLayoutAny>
 __device__ __forceinline__ void lm_start(const shape_batch& b, const KOpts& o, const Stamp& st,
                                          const float* p_init, const float* rec, int64_t s,
                                          LmShared& W, double* xs, int tid) {
@@ -239,7 +239,8 @@ __device__ __forceinline__ void lm_start(const shape_batch& b, const KOpts& o, c
       if (has(LIN, 6)) p[6] = 1.0;
       if (has(LIN, 7)) p[7] = 0.0;
       store_L<TEAM>(W, L, tid);
-      sweep_sums<DT, MODEL, LIN, TEAM>(b, st, make_trial(W.L.p, MODEL, o.moffat_beta), C, xs, tid);
+      sweep_sums<DT, MODEL, LIN, TEAM, LAYOUT>(b, st, make_trial(W.L.p, MODEL, o.moffat_beta), C, xs,
+                                               tid);
       L = load_L(W);
       if (!__builtin_isfinite(C[0])) {
         L.stt = SHAPE_ST_NONFINITE_INPUT;
@@ -256,7 +257,8 @@ __device__ __forceinline__ void lm_start(const shape_batch& b, const KOpts& o, c
     if (!(p[6] > 0.0)) L.stt |= SHAPE_ST_NONPOSITIVE_FLUX;
     L.nsweep = 1;
     store_L<TEAM>(W, L, tid);
-    sweep_sums<DT, MODEL, EM, TEAM>(b, st, make_trial(W.L.p, MODEL, o.moffat_beta), C, xs, tid);
+    sweep_sums<DT, MODEL, EM, TEAM, LAYOUT>(b, st, make_trial(W.L.p, MODEL, o.moffat_beta), C, xs,
+                                            tid);
     L = load_L(W);
     if (!__builtin_isfinite(C[0])) {
       L.stt = SHAPE_ST_NONFINITE_INPUT;
@@ -269,7 +271,7 @@ __device__ __forceinline__ void lm_start(const shape_batch& b, const KOpts& o, c
 // One LM trial from the current sums; the trial's sums go to the other buffer
 // and become current when the trial is accepted.  Sets W.L.done when the fit
 // has converged or stalled; the caller enforces max_iter_lm.
-template <int DT, int MODEL, uint32_t MASK, int TEAM>
+template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT = kLayoutAny>
 __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o, const Stamp& st,
                                            LmShared& W, double* xs, int tid) {
   constexpr uint32_t EM = eff_mask(MASK, MODEL);
@@ -366,7 +368,7 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
   if (W.smax < 0.0) return;
   // Phase 2: the sweep at the trial point (nothing else is live here).
   double* T = W.sums[cur ^ 1];
-  sweep_sums<DT, MODEL, EM, TEAM>(b, st, make_trial(W.pt, MODEL, o.moffat_beta), T, xs, tid);
+  sweep_sums<DT, MODEL, EM, TEAM, LAYOUT>(b, st, make_trial(W.pt, MODEL, o.moffat_beta), T, xs, tid);
   // Phase 3: amplitudes at the trial shape, then accept or reject.
   LmState L = load_L(W);
   double pt[8];

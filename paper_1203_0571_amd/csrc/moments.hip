@@ -63,7 +63,7 @@ __device__ inline Ksb ksb_from_moments(const Mom& M, double g1, double g2, doubl
   return k;
 }
 
-template <int DT>
+template <int DT, int SIDE>
 __global__ __launch_bounds__(kWave) void moments_kernel(shape_batch b, KOpts o, const float* rec_in,
                                                         float* rec_out, int32_t* iters,
                                                         uint32_t* status) {
@@ -88,7 +88,8 @@ __global__ __launch_bounds__(kWave) void moments_kernel(shape_batch b, KOpts o, 
       }
       continue;
     }
-    const int W = st.side;
+    const int W = SIDE ? SIDE : st.side;
+    const StampPixels<DT, SIDE> px(b, st, lane);
     const double sigw = r_in[SHAPE_REC_SIGW];
     const float skyf = r_in[SHAPE_REC_SKY0];
     const double c = -1.0 / (2.0 * sigw * sigw);           // W' = c W
@@ -104,8 +105,7 @@ __global__ __launch_bounds__(kWave) void moments_kernel(shape_batch b, KOpts o, 
       const float a12 = (float)(-4.0 * g2);
       const float xf = (float)x, yf = (float)y;
       Mom M = {};
-      for_pixels(W, [&](int k, int i, int j) {
-        float v = load_px<DT>(b.pixels, st.off, k, st.scale);
+      px.each([&](float v, int, int i, int j) {
         float t1 = (float)j - xf, t2 = (float)i - yf;
         float s11 = t1 * t1, s22 = t2 * t2, s12 = t1 * t2;
         float r2 = fmaf(a11, s11, fmaf(a22, s22, a12 * s12));
@@ -195,17 +195,30 @@ __global__ __launch_bounds__(kWave) void moments_kernel(shape_batch b, KOpts o, 
   }
 }
 
+template <int DT>
+void launch_side(int side, int64_t grid, const shape_batch& b, const KOpts& o, const float* rec_in,
+                 float* rec_out, int32_t* iters, uint32_t* status, hipStream_t stream) {
+  const dim3 g((unsigned)grid), t(kWave);
+  switch (side) {
+    case 8: hipLaunchKernelGGL((moments_kernel<DT, 8>), g, t, 0, stream, b, o, rec_in, rec_out, iters, status); break;
+    case 16: hipLaunchKernelGGL((moments_kernel<DT, 16>), g, t, 0, stream, b, o, rec_in, rec_out, iters, status); break;
+    case 32: hipLaunchKernelGGL((moments_kernel<DT, 32>), g, t, 0, stream, b, o, rec_in, rec_out, iters, status); break;
+    case 64: hipLaunchKernelGGL((moments_kernel<DT, 64>), g, t, 0, stream, b, o, rec_in, rec_out, iters, status); break;
+    default: hipLaunchKernelGGL((moments_kernel<DT, 0>), g, t, 0, stream, b, o, rec_in, rec_out, iters, status);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_moments(const shape_batch& b, const KOpts& o, const float* rec_in,
                           float* rec_out, int32_t* iters, uint32_t* status, hipStream_t stream) {
   const int64_t grid = b.n < (1ll << 30) ? b.n : (1ll << 30);
+  // A batch of one side that divides 64 keeps each stamp in registers.
+  const int side = (!b.side && register_side(b.side0)) ? b.side0 : 0;
   if (b.dtype == SHAPE_F32)
-    hipLaunchKernelGGL(moments_kernel<SHAPE_F32>, dim3((unsigned)grid), dim3(kWave), 0, stream, b,
-                       o, rec_in, rec_out, iters, status);
+    launch_side<SHAPE_F32>(side, grid, b, o, rec_in, rec_out, iters, status, stream);
   else
-    hipLaunchKernelGGL(moments_kernel<SHAPE_F16_SCALED>, dim3((unsigned)grid), dim3(kWave), 0,
-                       stream, b, o, rec_in, rec_out, iters, status);
+    launch_side<SHAPE_F16_SCALED>(side, grid, b, o, rec_in, rec_out, iters, status, stream);
   return hipGetLastError();
 }
 

@@ -1,12 +1,15 @@
 // Work-queue form of the profile fit for batches of uneven stamps.
 //
-// The stamps are ordered largest side first (a counting sort on the device),
-// every stamp's LM state lives in the caller's workspace, and one launch of the
-// persistent step kernel advances every still-active stamp by exactly one LM
-// trial (lm_iterate, the same code the fused kernel loops over).  Workgroups
-// pop stamps from an atomic cursor: stamps at or above `team_min_side` are
-// taken by the whole workgroup (TEAM waves on one stamp), the rest by single
-// waves.  A hipGraph of {reset, step} replays one LM iteration per launch.
+// The stamps are ordered by model (Sersic, then Moffat) and, within a model,
+// largest side first (a counting sort on the device); every stamp's LM state
+// lives in the caller's workspace, and a step advances every still-active
+// stamp by exactly one LM trial (lm_iterate, the same code the fused kernel
+// loops over).  A step is one persistent launch per model present, each
+// popping stamps of its own model's range from atomic cursors: stamps at or
+// above `team_min_side` are taken by the whole workgroup (TEAM waves on one
+// stamp), the rest by single waves.  One kernel per model keeps each kernel's
+// registers to its own sweep (a kernel holding both sweeps needs ~243 VGPRs,
+// two waves per SIMD).  A hipGraph of {reset, steps} replays one LM iteration.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -15,14 +18,20 @@
 namespace shape {
 namespace {
 
-constexpr int kBuckets = 256;  // side histogram; invalid stamps go to bucket 0
+// Histogram over (model, side): bucket = side for Sersic, 256 + side for
+// Moffat; stamps that cannot be processed go to bucket 0 (Sersic range).
+constexpr int kBuckets = 512;
 
 struct QHeader {
-  uint32_t next_big;    // cursor over order[0, nbig): team stamps
-  uint32_t next_small;  // cursor over order[nbig, n): single-wave stamps
-  uint32_t active;      // stamps still iterating after the last step
-  uint32_t nbig;
-  uint32_t pad[60];
+  uint32_t reserved0, reserved1;
+  uint32_t active;         // stamps still iterating after the last step
+  uint32_t reserved3;
+  uint32_t begin[2];       // order[begin[m], end[m]) holds model m's stamps
+  uint32_t nbig[2];        // ... of which [begin[m], nbig[m]) go to teams
+  uint32_t end[2];
+  uint32_t next_big[2];    // cursors, relative to begin[m] and nbig[m]
+  uint32_t next_small[2];
+  uint32_t pad[50];
 };
 static_assert(sizeof(QHeader) == 256, "header is one 256-byte block");
 
@@ -57,7 +66,7 @@ __host__ __device__ inline QView view(void* ws, int64_t n) {
 
 __device__ inline int bucket_of(const shape_batch& b, int64_t s) {
   const Stamp st = stamp_info(b, s);
-  return st.bad ? 0 : st.side;
+  return st.bad ? 0 : st.side + (st.model == SHAPE_MOFFAT ? 256 : 0);
 }
 
 // ---- ordering (largest side first) ----------------------------------------
@@ -68,29 +77,56 @@ __global__ void clear_kernel(QHeader* hdr, uint32_t* buckets) {
   for (int k = t; k < kBuckets; k += blockDim.x) buckets[k] = 0u;
 }
 
+// Counts per side: a histogram per workgroup in LDS, then one global atomic
+// per non-empty bucket (a uniform batch would otherwise serialise every
+// stamp on one address).
 __global__ void hist_kernel(shape_batch b, uint32_t* buckets) {
+  __shared__ uint32_t h[kBuckets];
+  for (int k = threadIdx.x; k < kBuckets; k += blockDim.x) h[k] = 0u;
+  __syncthreads();
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < b.n;
        s += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&buckets[bucket_of(b, s)], 1u);
+    atomicAdd(&h[bucket_of(b, s)], 1u);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kBuckets; k += blockDim.x)
+    if (h[k]) atomicAdd(&buckets[k], h[k]);
 }
 
-// One thread turns the histogram into start cursors, largest side first.
+// One thread turns the histogram into start cursors: the Sersic range
+// (largest side first, unprocessable stamps last), then the Moffat range.
 __global__ void scan_kernel(QHeader* hdr, uint32_t* buckets, int team_min_side) {
   if (threadIdx.x != 0) return;
-  uint32_t pos = 0, nbig = 0;
-  for (int side = kBuckets - 1; side >= 0; --side) {
-    const uint32_t c = buckets[side];
-    buckets[side] = pos;
-    pos += c;
-    if (side >= team_min_side && side > 0) nbig = pos;
+  uint32_t pos = 0;
+  for (int m = 0; m < 2; ++m) {
+    hdr->begin[m] = pos;
+    uint32_t nbig = pos;
+    for (int side = 255; side >= (m == 0 ? 0 : 1); --side) {
+      const int k = side + 256 * m;
+      const uint32_t c = buckets[k];
+      buckets[k] = pos;
+      pos += c;
+      if (side >= team_min_side && side > 0) nbig = pos;
+    }
+    hdr->nbig[m] = nbig;
+    hdr->end[m] = pos;
   }
-  hdr->nbig = nbig;
 }
 
+// Places every stamp at its side's cursor: each workgroup counts its own
+// stamps per side in LDS, reserves one range per side with a single global
+// atomic, then hands out places inside its ranges with LDS atomics.
 __global__ void scatter_kernel(shape_batch b, uint32_t* buckets, int32_t* order) {
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < b.n;
-       s += (int64_t)gridDim.x * blockDim.x)
-    order[atomicAdd(&buckets[bucket_of(b, s)], 1u)] = (int32_t)s;
+  __shared__ uint32_t h[kBuckets];
+  for (int k = threadIdx.x; k < kBuckets; k += blockDim.x) h[k] = 0u;
+  __syncthreads();
+  const int64_t s0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t ds = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s = s0; s < b.n; s += ds) atomicAdd(&h[bucket_of(b, s)], 1u);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kBuckets; k += blockDim.x)
+    h[k] = h[k] ? atomicAdd(&buckets[k], h[k]) : 0u;
+  __syncthreads();
+  for (int64_t s = s0; s < b.n; s += ds) order[atomicAdd(&h[bucket_of(b, s)], 1u)] = (int32_t)s;
 }
 
 // ---- per-stamp work -------------------------------------------------------
@@ -142,7 +178,7 @@ __device__ inline LmState load_lm(const QState* q) {
 }
 
 // Starting point of one stamp (lm_start), written to its state row.
-template <int DT, uint32_t MASK, int TEAM>
+template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT = kLayoutAny>
 __device__ inline void start_one(const shape_batch& b, const KOpts& o, const float* p_init,
                                  const float* rec, QState* state, int64_t s, LmShared& W,
                                  double* xs, int tid) {
@@ -163,10 +199,7 @@ __device__ inline void start_one(const shape_batch& b, const KOpts& o, const flo
     store_state<TEAM>(q, W, false, tid);
     return;
   }
-  if (st.model == SHAPE_SERSIC)
-    lm_start<DT, SHAPE_SERSIC, MASK, TEAM>(b, o, st, p_init, rec, s, W, xs, tid);
-  else
-    lm_start<DT, SHAPE_MOFFAT, MASK, TEAM>(b, o, st, p_init, rec, s, W, xs, tid);
+  lm_start<DT, MODEL, MASK, TEAM, LAYOUT>(b, o, st, p_init, rec, s, W, xs, tid);
   if (tid == 0 && !W.L.done && W.L.it >= o.max_iter_lm) W.L.done = 1;
   team_sync<TEAM>();
   store_state<TEAM>(q, W, true, tid);
@@ -174,17 +207,14 @@ __device__ inline void start_one(const shape_batch& b, const KOpts& o, const flo
 
 // One LM trial of one stamp, state in and out of its row.  Returns whether
 // the stamp is still active afterwards.
-template <int DT, uint32_t MASK, int TEAM>
+template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT = kLayoutAny>
 __device__ inline bool step_one(const shape_batch& b, const KOpts& o, QState* state, int64_t s,
                                 LmShared& W, double* xs, int tid) {
   QState* q = state + s;
   if (q->done) return false;
   const Stamp st = stamp_info(b, s);
   load_state<TEAM>(q, W, tid);
-  if (st.model == SHAPE_SERSIC)
-    lm_iterate<DT, SHAPE_SERSIC, MASK, TEAM>(b, o, st, W, xs, tid);
-  else
-    lm_iterate<DT, SHAPE_MOFFAT, MASK, TEAM>(b, o, st, W, xs, tid);
+  lm_iterate<DT, MODEL, MASK, TEAM, LAYOUT>(b, o, st, W, xs, tid);
   if (tid == 0 && !W.L.done && W.L.it >= o.max_iter_lm) W.L.done = 1;
   team_sync<TEAM>();
   const bool active = !W.L.done;
@@ -192,47 +222,51 @@ __device__ inline bool step_one(const shape_batch& b, const KOpts& o, QState* st
   return active;
 }
 
-// Persistent pass over the queue: team phase over order[0, nbig), then every
-// wave on its own over order[nbig, n).  Every workgroup leaves once both
-// cursors have passed the end, so the grid always drains.
-template <int DT, uint32_t MASK, int TEAM, bool START>
-__global__ __launch_bounds__(kWave* TEAM) void queue_kernel(shape_batch b, KOpts o, void* ws,
-                                                            const float* p_init, const float* rec) {
+// Persistent pass over one model's range of the queue: team phase over
+// order[begin, nbig), then every wave on its own over order[nbig, end).
+// Every workgroup leaves once both cursors have passed the end, so the grid
+// always drains.  Four waves per SIMD, as the fused fit.  LAYOUT applies to
+// the single-wave phase (kLayoutRows only for batches of one side that
+// divides 64, as in the fused fit).
+template <int DT, int MODEL, uint32_t MASK, int TEAM, bool START, int LAYOUT>
+__global__ __launch_bounds__(kWave* TEAM, 4) void queue_kernel(shape_batch b, KOpts o, void* ws,
+                                                               const float* p_init,
+                                                               const float* rec) {
   __shared__ LmShared W[TEAM];
   __shared__ double xs[TEAM * kSums];
   __shared__ uint32_t s_idx;
   const QView v = view(ws, b.n);
-  const uint32_t n = (uint32_t)b.n;
-  const uint32_t nbig = TEAM > 1 ? v.hdr->nbig : 0u;
+  const uint32_t begin = v.hdr->begin[MODEL], end = v.hdr->end[MODEL];
+  const uint32_t nbig = TEAM > 1 ? v.hdr->nbig[MODEL] : begin;
   const int tid = threadIdx.x;
   const int wave = tid / kWave, lane = tid & (kWave - 1);
   uint32_t still = 0;  // active stamps seen by this thread (thread 0 / lane 0 only)
   if constexpr (TEAM > 1) {
     for (;;) {
-      if (tid == 0) s_idx = atomicAdd(&v.hdr->next_big, 1u);
+      if (tid == 0) s_idx = atomicAdd(&v.hdr->next_big[MODEL], 1u);
       __syncthreads();
-      const uint32_t idx = s_idx;
+      const uint32_t idx = s_idx + begin;
       __syncthreads();
       if (idx >= nbig) break;
       const int64_t s = v.order[idx];
       if (START) {
-        start_one<DT, MASK, TEAM>(b, o, p_init, rec, v.state, s, W[0], xs, tid);
+        start_one<DT, MODEL, MASK, TEAM>(b, o, p_init, rec, v.state, s, W[0], xs, tid);
         __syncthreads();
-      } else if (step_one<DT, MASK, TEAM>(b, o, v.state, s, W[0], xs, tid)) {
+      } else if (step_one<DT, MODEL, MASK, TEAM>(b, o, v.state, s, W[0], xs, tid)) {
         if (tid == 0) ++still;
       }
     }
   }
   for (;;) {
     uint32_t idx = 0;
-    if (lane == 0) idx = atomicAdd(&v.hdr->next_small, 1u);
+    if (lane == 0) idx = atomicAdd(&v.hdr->next_small[MODEL], 1u);
     idx = __builtin_amdgcn_readfirstlane(idx) + nbig;
-    if (idx >= n) break;
+    if (idx >= end) break;
     const int64_t s = v.order[idx];
     if (START) {
-      start_one<DT, MASK, 1>(b, o, p_init, rec, v.state, s, W[wave], nullptr, lane);
+      start_one<DT, MODEL, MASK, 1, LAYOUT>(b, o, p_init, rec, v.state, s, W[wave], nullptr, lane);
       wave_sync();
-    } else if (step_one<DT, MASK, 1>(b, o, v.state, s, W[wave], nullptr, lane)) {
+    } else if (step_one<DT, MODEL, MASK, 1, LAYOUT>(b, o, v.state, s, W[wave], nullptr, lane)) {
       if (lane == 0) ++still;
     }
   }
@@ -241,8 +275,8 @@ __global__ __launch_bounds__(kWave* TEAM) void queue_kernel(shape_batch b, KOpts
 
 __global__ void reset_kernel(QHeader* hdr) {
   if (threadIdx.x == 0) {
-    hdr->next_big = 0u;
-    hdr->next_small = 0u;
+    hdr->next_big[0] = hdr->next_big[1] = 0u;
+    hdr->next_small[0] = hdr->next_small[1] = 0u;
     hdr->active = 0u;
   }
 }
@@ -277,15 +311,27 @@ __global__ void finish_kernel(shape_batch b, KOpts o, void* ws, float* p_out, fl
   }
 }
 
-template <int DT, uint32_t MASK, int TEAM, bool START>
+template <int DT, int MODEL, uint32_t MASK, int TEAM, bool START, int LAYOUT = kLayoutAny>
 const void* queue_kernel_ptr() {
-  return reinterpret_cast<const void*>(&queue_kernel<DT, MASK, TEAM, START>);
+  return reinterpret_cast<const void*>(&queue_kernel<DT, MODEL, MASK, TEAM, START, LAYOUT>);
 }
 
-template <bool START>
-const void* pick_kernel(int dtype, uint32_t mask, int team) {
+template <int MODEL, bool START>
+const void* pick_kernel(int dtype, uint32_t mask, int team, bool rows) {
+  if constexpr (MODEL == SHAPE_SERSIC) {
+    if (rows && team == 1) {
+      if (dtype == SHAPE_F32 && mask == kMaskAll)
+        return queue_kernel_ptr<SHAPE_F32, MODEL, kMaskAll, 1, START, kLayoutRows>();
+      if (dtype == SHAPE_F32 && mask == kMaskSize)
+        return queue_kernel_ptr<SHAPE_F32, MODEL, kMaskSize, 1, START, kLayoutRows>();
+      if (dtype == SHAPE_F16_SCALED && mask == kMaskAll)
+        return queue_kernel_ptr<SHAPE_F16_SCALED, MODEL, kMaskAll, 1, START, kLayoutRows>();
+      if (dtype == SHAPE_F16_SCALED && mask == kMaskSize)
+        return queue_kernel_ptr<SHAPE_F16_SCALED, MODEL, kMaskSize, 1, START, kLayoutRows>();
+    }
+  }
 #define SHAPE_Q(DT, M, T) \
-  if (dtype == DT && mask == M && team == T) return queue_kernel_ptr<DT, M, T, START>();
+  if (dtype == DT && mask == M && team == T) return queue_kernel_ptr<DT, MODEL, M, T, START>();
   SHAPE_Q(SHAPE_F32, kMaskAll, 1)
   SHAPE_Q(SHAPE_F32, kMaskAll, 2)
   SHAPE_Q(SHAPE_F32, kMaskAll, 4)
@@ -311,16 +357,29 @@ hipError_t resident_grid(const void* fn, int team, int* grid) {
 
 hipError_t launch_queue_pass(const shape_batch& b, const KOpts& o, void* ws, const float* p_init,
                              const float* rec, const QCfg& cfg, bool start, hipStream_t stream) {
-  const void* fn = start ? pick_kernel<true>(b.dtype, o.free_mask, cfg.team)
-                         : pick_kernel<false>(b.dtype, o.free_mask, cfg.team);
-  if (!fn) return hipErrorInvalidValue;
-  int grid = cfg.grid;
-  if (grid <= 0) {
-    hipError_t e = resident_grid(fn, cfg.team, &grid);
+  // Sersic always (it also retires unprocessable stamps); Moffat when the
+  // batch carries a model array.
+  const int models = b.model ? 2 : 1;
+  const bool rows = !b.side && !b.model && rows_layout_fits(b.side0);
+  for (int m = 0; m < models; ++m) {
+    const void* fn;
+    if (m == 0)
+      fn = start ? pick_kernel<SHAPE_SERSIC, true>(b.dtype, o.free_mask, cfg.team, rows)
+                 : pick_kernel<SHAPE_SERSIC, false>(b.dtype, o.free_mask, cfg.team, rows);
+    else
+      fn = start ? pick_kernel<SHAPE_MOFFAT, true>(b.dtype, o.free_mask, cfg.team, rows)
+                 : pick_kernel<SHAPE_MOFFAT, false>(b.dtype, o.free_mask, cfg.team, rows);
+    if (!fn) return hipErrorInvalidValue;
+    int grid = cfg.grid;
+    if (grid <= 0) {
+      hipError_t e = resident_grid(fn, cfg.team, &grid);
+      if (e != hipSuccess) return e;
+    }
+    void* args[] = {(void*)&b, (void*)&o, &ws, (void*)&p_init, (void*)&rec};
+    hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kWave * cfg.team), args, 0, stream);
     if (e != hipSuccess) return e;
   }
-  void* args[] = {(void*)&b, (void*)&o, &ws, (void*)&p_init, (void*)&rec};
-  return hipLaunchKernel(fn, dim3(grid), dim3(kWave * cfg.team), args, 0, stream);
+  return hipSuccess;
 }
 
 }  // namespace

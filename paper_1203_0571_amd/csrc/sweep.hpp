@@ -146,7 +146,18 @@ __device__ __forceinline__ Trial<T> make_trial(const double* p, int model, doubl
 }
 
 // One sweep: model, residual, Jacobian columns in EM, and their sums.
-template <int DT, int MODEL, uint32_t EM, int STRIDE = kWave, typename T = float>
+// Pixel layouts of a sweep: kLayoutAny walks any side with the lane stride;
+// kLayoutRows is for a wave alone on a stamp whose side divides 64 with at
+// least 64 pixels (8, 16, 32, 64): every lane then keeps one column, steps
+// 64 / side rows at a time, and the trip count is the same for all lanes.
+constexpr int kLayoutAny = 0;
+constexpr int kLayoutRows = 1;
+__host__ __device__ inline constexpr bool rows_layout_fits(int side) {
+  return side == 8 || side == 16 || side == 32 || side == 64;
+}
+
+template <int DT, int MODEL, uint32_t EM, int STRIDE = kWave, typename T = float,
+          int LAYOUT = kLayoutAny>
 __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, const Trial<T>& t,
                              Acc<EM, T>& acc, int tid = -1) {
   using A = Arith<T>;
@@ -155,11 +166,8 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
   for (int k = 0; k < 8; ++k) acc.g[k] = 0.0;
 #pragma unroll
   for (int k = 0; k < 36; ++k) acc.A[k] = (T)0;
-  for_pixels<STRIDE>(st.side, [&](int k, int i, int j) {
-    const T d = (T)load_px<DT>(b.pixels, st.off, k, st.scale);
-    const T u1 = (T)j - t.x0, u2 = (T)i - t.y0;
-    const T v1 = A::fma(t.a11, u1, t.a12 * u2);
-    const T v2 = A::fma(t.a12, u1, t.a22 * u2);
+  // d = data, (u1, u2) = offset from the centre, (v1, v2) = S(e) u
+  auto pixel = [&](const T d, const T u1, const T u2, const T v1, const T v2) {
     const T q = A::fma(v1, v1, v2 * v2);
     T R2 = q * t.invD;
     const bool floored = R2 < A::kR2Floor;
@@ -212,13 +220,40 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
 #pragma unroll
       for (int c = a; c < 8; ++c) {
         if (!has(EM, c)) continue;
+        if (c == 7 && a == 7) continue;   // the count of pixels, set by the caller
         if (c == 7)
           acc.A[tri(a, c)] += J[a];
         else
           acc.A[tri(a, c)] = A::fma(J[a], J[c], acc.A[tri(a, c)]);
       }
     }
-  }, tid);
+  };
+  if constexpr (LAYOUT == kLayoutRows) {
+    static_assert(STRIDE == kWave, "the row layout is for a wave alone on its stamp");
+    const int lane = tid < 0 ? (int)(threadIdx.x & (kWave - 1)) : tid;
+    const int sd = st.side;                      // 8, 16, 32 or 64
+    const T u1 = (T)(lane & (sd - 1)) - t.x0;
+    const T c1 = t.a11 * u1, c2 = t.a12 * u1;
+    const T di = (T)(kWave / sd);
+    T fi = (T)(lane / sd);
+    const int nstep = st.npix / kWave;
+    const void* sp = stamp_base<DT>(b, st);
+    uint32_t k = (uint32_t)lane;
+#pragma unroll 1
+    for (int m = 0; m < nstep; ++m) {
+      const T d = (T)load_rel<DT>(sp, k, st.scale);
+      const T u2 = fi - t.y0;
+      pixel(d, u1, u2, A::fma(t.a12, u2, c1), A::fma(t.a22, u2, c2));
+      fi += di;
+      k += kWave;
+    }
+  } else {
+    for_pixels<STRIDE>(st.side, [&](int k, int i, int j) {
+      const T d = (T)load_px<DT>(b.pixels, st.off, k, st.scale);
+      const T u1 = (T)j - t.x0, u2 = (T)i - t.y0;
+      pixel(d, u1, u2, A::fma(t.a11, u1, t.a12 * u2), A::fma(t.a12, u1, t.a22 * u2));
+    }, tid);
+  }
 }
 
 // Reduce a sweep's per-lane partial sums over the wave and let lane 0 store

@@ -34,6 +34,27 @@ __device__ __forceinline__ float frame_px(const shape_frames& f, int64_t base, i
   }
 }
 
+// Four consecutive pixels from a 4-aligned index (frames whose pixel count
+// is a multiple of 4 on a 16-byte aligned buffer).
+template <int DT>
+__device__ __forceinline__ void load4(const shape_frames& f, int64_t base, int64_t k, float scale,
+                                      float (&v)[4]) {
+  if constexpr (DT == SHAPE_F32) {
+    const float4 q = *reinterpret_cast<const float4*>(static_cast<const float*>(f.pixels) + base + k);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+  } else {
+    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+    const h4 q = *reinterpret_cast<const h4*>(static_cast<const _Float16*>(f.pixels) + base + k);
+    v[0] = (float)q[0] * scale;
+    v[1] = (float)q[1] * scale;
+    v[2] = (float)q[2] * scale;
+    v[3] = (float)q[3] * scale;
+  }
+}
+
 // Sum over the workgroup in a fixed order (wave DPP sums, then waves 0..3).
 __device__ __forceinline__ double block_sum(double v, double* red) {
   const int tid = threadIdx.x, w = tid / kWave;
@@ -57,7 +78,7 @@ __device__ __forceinline__ int ceil_sqrt(int64_t d2) {
 
 template <int DT>
 __global__ __launch_bounds__(kFrameThreads) void detect_kernel(shape_frames f, int max_side,
-                                                               int nbins, float* info,
+                                                               int nbins, bool vec4, float* info,
                                                                int32_t* peak, int32_t* box,
                                                                uint32_t* status) {
   extern __shared__ long long bins[];   // nbins
@@ -92,16 +113,28 @@ __global__ __launch_bounds__(kFrameThreads) void detect_kernel(shape_frames f, i
     int64_t bk = npix;
     bool finite = true;
     double tot = 0.0, amax = 0.0;
-    for (int64_t k = tid; k < npix; k += kFrameThreads) {
-      const float v = frame_px<DT>(f, base, k, scale);
+    auto visit = [&](float v, int64_t k) {
       finite = finite && __builtin_isfinite(v);
-      if (v > best) {
+      if (v > best) {  // each thread's k increases: ties keep the first index
         best = v;
         bk = k;
       }
       const double d = (double)v - sky;
       tot += d;
       amax = fmax(amax, fabs(d));
+    };
+    if (vec4) {
+      // four pixels per load (16 B FP32 / 8 B FP16), two loads in flight
+      const int64_t n4 = npix >> 2;
+#pragma unroll 2
+      for (int64_t q = tid; q < n4; q += kFrameThreads) {
+        float v[4];
+        load4<DT>(f, base, q * 4, scale, v);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) visit(v[c], q * 4 + c);
+      }
+    } else {
+      for (int64_t k = tid; k < npix; k += kFrameThreads) visit(frame_px<DT>(f, base, k, scale), k);
     }
     const bool all_finite = __syncthreads_and(finite);
     if (!all_finite) {
@@ -304,12 +337,15 @@ hipError_t launch_frame_detect(const shape_frames& f, int max_side, float* info,
   const int nbins = frame_bins(f.height, f.width);
   const size_t lds = (size_t)nbins * sizeof(long long);
   const int64_t grid = f.n < (1ll << 30) ? f.n : (1ll << 30);
+  const int64_t npix = (int64_t)f.height * f.width;
+  const size_t align = f.dtype == SHAPE_F32 ? 16 : 8;
+  const bool vec4 = npix % 4 == 0 && reinterpret_cast<uintptr_t>(f.pixels) % align == 0;
   if (f.dtype == SHAPE_F32)
     hipLaunchKernelGGL(detect_kernel<SHAPE_F32>, dim3((unsigned)grid), dim3(kFrameThreads), lds,
-                       stream, f, max_side, nbins, info, peak, box, status);
+                       stream, f, max_side, nbins, vec4, info, peak, box, status);
   else
     hipLaunchKernelGGL(detect_kernel<SHAPE_F16_SCALED>, dim3((unsigned)grid), dim3(kFrameThreads),
-                       lds, stream, f, max_side, nbins, info, peak, box, status);
+                       lds, stream, f, max_side, nbins, vec4, info, peak, box, status);
   return hipGetLastError();
 }
 

@@ -21,6 +21,15 @@ namespace {
 // Histogram over (model, side): bucket = side for Sersic, 256 + side for
 // Moffat; stamps that cannot be processed go to bucket 0 (Sersic range).
 constexpr int kBuckets = 512;
+constexpr int kChunk = 8;      // stamps per cursor pop
+// Cursors per (model, phase): workgroup g pops from cursor g % kCursors, and
+// cursor c hands out the chunks c, c + kCursors, c + 2 kCursors, ... of the
+// range, so every cursor sees the whole size mix.  Each cursor has its own
+// 128-byte line: pops on different cursors do not contend (consecutive
+// workgroups also land on different XCDs).
+constexpr int kCursors = 8;
+constexpr int kCursorStride = 32;  // uint32 per cursor line
+constexpr size_t kCursorBytes = 2 * 2 * kCursors * kCursorStride * 4;
 
 struct QHeader {
   uint32_t reserved0, reserved1;
@@ -29,9 +38,7 @@ struct QHeader {
   uint32_t begin[2];       // order[begin[m], end[m]) holds model m's stamps
   uint32_t nbig[2];        // ... of which [begin[m], nbig[m]) go to teams
   uint32_t end[2];
-  uint32_t next_big[2];    // cursors, relative to begin[m] and nbig[m]
-  uint32_t next_small[2];
-  uint32_t pad[50];
+  uint32_t pad[54];
 };
 static_assert(sizeof(QHeader) == 256, "header is one 256-byte block");
 
@@ -47,6 +54,7 @@ static_assert(sizeof(QState) % 64 == 0, "state rows stay 64-byte aligned");
 
 struct QView {
   QHeader* hdr;
+  uint32_t* cursors;  // [model][phase: 0 team, 1 single][kCursors][kCursorStride]
   uint32_t* buckets;
   int32_t* order;
   QState* state;
@@ -58,9 +66,11 @@ __host__ __device__ inline QView view(void* ws, int64_t n) {
   char* c = static_cast<char*>(ws);
   QView v;
   v.hdr = reinterpret_cast<QHeader*>(c);
-  v.buckets = reinterpret_cast<uint32_t*>(c + 256);
-  v.order = reinterpret_cast<int32_t*>(c + 256 + align256(kBuckets * 4));
-  v.state = reinterpret_cast<QState*>(c + 256 + align256(kBuckets * 4) + align256(n * 4));
+  v.cursors = reinterpret_cast<uint32_t*>(c + 256);
+  c += 256 + kCursorBytes;
+  v.buckets = reinterpret_cast<uint32_t*>(c);
+  v.order = reinterpret_cast<int32_t*>(c + align256(kBuckets * 4));
+  v.state = reinterpret_cast<QState*>(c + align256(kBuckets * 4) + align256(n * 4));
   return v;
 }
 
@@ -240,45 +250,64 @@ __global__ __launch_bounds__(kWave* TEAM, 4) void queue_kernel(shape_batch b, KO
   const uint32_t nbig = TEAM > 1 ? v.hdr->nbig[MODEL] : begin;
   const int tid = threadIdx.x;
   const int wave = tid / kWave, lane = tid & (kWave - 1);
+  const uint32_t cur = blockIdx.x % kCursors;
+  uint32_t* big_cursor = v.cursors + ((MODEL * 2 + 0) * kCursors + cur) * kCursorStride;
+  uint32_t* small_cursor = v.cursors + ((MODEL * 2 + 1) * kCursors + cur) * kCursorStride;
   uint32_t still = 0;  // active stamps seen by this thread (thread 0 / lane 0 only)
+  // Stamps are popped kChunk at a time: one atomic on a shared cursor costs
+  // about as much as a stamp's LM step, and most stamps of a late step are
+  // already done (their rows are skipped after a flag read).
   if constexpr (TEAM > 1) {
     for (;;) {
-      if (tid == 0) s_idx = atomicAdd(&v.hdr->next_big[MODEL], 1u);
+      if (tid == 0) s_idx = atomicAdd(big_cursor, 1u);
       __syncthreads();
-      const uint32_t idx = s_idx + begin;
+      const uint32_t first = begin + (s_idx * kCursors + cur) * kChunk;
       __syncthreads();
-      if (idx >= nbig) break;
-      const int64_t s = v.order[idx];
-      if (START) {
-        start_one<DT, MODEL, MASK, TEAM>(b, o, p_init, rec, v.state, s, W[0], xs, tid);
-        __syncthreads();
-      } else if (step_one<DT, MODEL, MASK, TEAM>(b, o, v.state, s, W[0], xs, tid)) {
-        if (tid == 0) ++still;
+      if (first >= nbig) break;
+      for (uint32_t idx = first; idx < first + kChunk && idx < nbig; ++idx) {
+        const int64_t s = v.order[idx];
+        if (START) {
+          start_one<DT, MODEL, MASK, TEAM>(b, o, p_init, rec, v.state, s, W[0], xs, tid);
+          __syncthreads();
+        } else if (step_one<DT, MODEL, MASK, TEAM>(b, o, v.state, s, W[0], xs, tid)) {
+          if (tid == 0) ++still;
+        }
       }
     }
   }
   for (;;) {
-    uint32_t idx = 0;
-    if (lane == 0) idx = atomicAdd(&v.hdr->next_small[MODEL], 1u);
-    idx = __builtin_amdgcn_readfirstlane(idx) + nbig;
-    if (idx >= end) break;
-    const int64_t s = v.order[idx];
-    if (START) {
-      start_one<DT, MODEL, MASK, 1, LAYOUT>(b, o, p_init, rec, v.state, s, W[wave], nullptr, lane);
-      wave_sync();
-    } else if (step_one<DT, MODEL, MASK, 1, LAYOUT>(b, o, v.state, s, W[wave], nullptr, lane)) {
-      if (lane == 0) ++still;
+    uint32_t first = 0;
+    if (lane == 0) first = atomicAdd(small_cursor, 1u);
+    first = nbig + (__builtin_amdgcn_readfirstlane(first) * kCursors + cur) * kChunk;
+    if (first >= end) break;
+    // lanes 0 .. kChunk-1 look up the chunk's stamps and whether they still iterate
+    int32_t sl = 0;
+    bool todo = false;
+    if (lane < kChunk && first + lane < end) {
+      sl = v.order[first + lane];
+      todo = START || !v.state[sl].done;
+    }
+    uint64_t mask = __ballot(todo);
+    while (mask) {
+      const int l = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      const int64_t s = __builtin_amdgcn_readlane(sl, l);
+      if (START) {
+        start_one<DT, MODEL, MASK, 1, LAYOUT>(b, o, p_init, rec, v.state, s, W[wave], nullptr,
+                                              lane);
+        wave_sync();
+      } else if (step_one<DT, MODEL, MASK, 1, LAYOUT>(b, o, v.state, s, W[wave], nullptr, lane)) {
+        if (lane == 0) ++still;
+      }
     }
   }
   if (!START && lane == 0 && still) atomicAdd(&v.hdr->active, still);
 }
 
-__global__ void reset_kernel(QHeader* hdr) {
-  if (threadIdx.x == 0) {
-    hdr->next_big[0] = hdr->next_big[1] = 0u;
-    hdr->next_small[0] = hdr->next_small[1] = 0u;
-    hdr->active = 0u;
-  }
+__global__ void reset_kernel(QHeader* hdr, uint32_t* cursors) {
+  const int t = threadIdx.x;
+  if (t < 4 * kCursors) cursors[t * kCursorStride] = 0u;
+  if (t == 0) hdr->active = 0u;
 }
 
 // Outputs from the state rows, one thread per stamp.
@@ -385,7 +414,8 @@ hipError_t launch_queue_pass(const shape_batch& b, const KOpts& o, void* ws, con
 }  // namespace
 
 size_t queue_workspace_bytes(int64_t n) {
-  return 256 + align256(kBuckets * 4) + align256((size_t)n * 4) + (size_t)n * sizeof(QState);
+  return 256 + kCursorBytes + align256(kBuckets * 4) + align256((size_t)n * 4) +
+         (size_t)n * sizeof(QState);
 }
 
 hipError_t launch_queue_start(const shape_batch& b, const KOpts& o, void* ws, const float* p_init,
@@ -401,7 +431,7 @@ hipError_t launch_queue_start(const shape_batch& b, const KOpts& o, void* ws, co
                      v.order);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(kWave), 0, stream, v.hdr);
+  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(kWave), 0, stream, v.hdr, v.cursors);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_queue_pass(b, o, ws, p_init, rec, cfg, true, stream);
@@ -410,7 +440,7 @@ hipError_t launch_queue_start(const shape_batch& b, const KOpts& o, void* ws, co
 hipError_t launch_queue_step(const shape_batch& b, const KOpts& o, void* ws, const QCfg& cfg,
                              hipStream_t stream) {
   const QView v = view(ws, b.n);
-  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(kWave), 0, stream, v.hdr);
+  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(kWave), 0, stream, v.hdr, v.cursors);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_queue_pass(b, o, ws, nullptr, nullptr, cfg, false, stream);

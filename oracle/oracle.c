@@ -594,6 +594,11 @@ static int schur_nl(const double* jtj, const int* nidx, int nn, const int* lidx,
 /* (lambda / 10, floor 1e-9).  Converged when an accepted step has           */
 /* max_k |delta_k| / s_k < tol_lm, s = (1, 1, 1, 1, Re, n); stalled when      */
 /* lambda exceeds 1e10.                                                      */
+/* With linear_init = 0 the free amplitudes are not profiled: they start at  */
+/* their linear optimum at the starting shape and are then searched by the   */
+/* same LM together with the shape parameters (the plain form the           */
+/* paper's split is compared with), with s_6 = |I0| and s_7 = sigma in the   */
+/* stopping rule.                                                            */
 /* ------------------------------------------------------------------------ */
 void orc_fit(const double* img, int side, double sigma, int kind, const double* p_init,
              const orc_opts* o, double* p_out, double* chi2_out, int* iters,
@@ -604,11 +609,12 @@ void orc_fit(const double* img, int side, double sigma, int kind, const double* 
   if (kind == ORC_MOFFAT) mask &= ~(1u << 5);
   uint32_t lin = o->linear_init ? (mask & 0xC0u) : 0u;
   int nidx[8], lidx[2], nn = 0, nl = 0;
-  for (int k = 0; k < 6; ++k)
-    if (mask & (1u << k)) nidx[nn++] = k;
-  for (int k = 6; k < 8; ++k)
+  for (int k = 0; k < 8; ++k) {
+    if (!(mask & (1u << k))) continue;
     if (lin & (1u << k)) lidx[nl++] = k;
-  if (lin) orc_linear_subset(img, side, p, kind, lin, &p[6], &p[7]);
+    else nidx[nn++] = k;
+  }
+  if (mask & 0xC0u) orc_linear_subset(img, side, p, kind, mask & 0xC0u, &p[6], &p[7]);
   if (!(p[6] > 0.0)) *status |= ORC_NONPOSITIVE_FLUX;
   double chi2 = orc_chi2(img, side, sigma, p, kind, grad, jtj);
   double lambda = o->lambda0;
@@ -629,7 +635,7 @@ void orc_fit(const double* img, int side, double sigma, int kind, const double* 
     }
     memcpy(pt, p, sizeof pt);
     double smax = 0.0;
-    double scl[6] = {1.0, 1.0, 1.0, 1.0, p[4], p[5]};
+    double scl[8] = {1.0, 1.0, 1.0, 1.0, p[4], p[5], fabs(p[6]), sigma};
     for (int a = 0; a < nn; ++a) {
       pt[nidx[a]] += rhs[a];
       double r = fabs(rhs[a]) / scl[nidx[a]];
@@ -663,7 +669,7 @@ void orc_fit(const double* img, int side, double sigma, int kind, const double* 
   if (perr) {
     int idx[8], nf = 0;
     for (int k = 0; k < 8; ++k)
-      if ((k < 6 && (mask & (1u << k))) || (lin & (1u << k))) idx[nf++] = k;
+      if (mask & (1u << k)) idx[nf++] = k;
     for (int k = 0; k < 8; ++k) perr[k] = 0.0;
     /* sigma_p = sqrt(diag(A^-1)) over all fitted parameters, column by column */
     for (int c = 0; c < nf; ++c) {

@@ -47,7 +47,8 @@ typedef struct {
   double   n0;                 /* initial Sersic index */
   double   moffat_beta;        /* fixed Moffat index for stars */
   uint32_t free_mask;          /* bit k set => p[k] is fitted */
-  int      linear_init;        /* profile free (I0, sky) out linearly at every point */
+  int      linear_init;        /* 1: profile free (I0, sky) out linearly at every point;
+                                  0: search them with the shape by LM (linear start) */
 } orc_opts;
 
 void orc_default_opts(orc_opts* o);

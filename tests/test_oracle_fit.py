@@ -159,3 +159,49 @@ def test_gaussian_workload_pipeline():
     assert np.median(np.abs(d[:, 0])) < 0.05
     assert np.median(np.abs(d[:, 2:4])) < 0.02
     assert np.median(np.abs(r["p"][conv, 5] / 0.5 - 1)) < 0.05
+
+
+# ---- the unprofiled form (linear_init = 0): amplitudes searched by LM -------
+
+@pytest.mark.parametrize("truth", [
+    (23.7, 24.2, 0.21, -0.13, 3.2, 0.7, 500.0, 10.0),
+    (22.9, 23.1, -0.35, 0.30, 4.5, 1.6, 80.0, 10.0),
+])
+def test_unprofiled_noiseless_recovery(truth):
+    """Fitting (I0, sky) with the shape parameters recovers noiseless stamps."""
+    truth = np.array(truth)
+    img = _noiseless(truth, 48)
+    p0 = truth * np.array([1, 1, 0.8, 1.2, 1.25, 0.8, 1, 1]) + np.array([0.4, -0.3, 0, 0, 0, 0, 0, 0])
+    r = oracle.fit(img, 1.0, p0, o=oracle.opts(tol_lm=1e-12, max_iter_lm=400, linear_init=0))
+    assert r["status"] & oracle.CONVERGED
+    np.testing.assert_allclose(r["p"][:4], truth[:4], atol=1e-7)
+    np.testing.assert_allclose(r["p"][4:], truth[4:], rtol=1e-7)
+
+
+@pytest.mark.parametrize("mask", [0xF0, 0xFF])
+def test_unprofiled_and_profiled_reach_the_same_minimum(mask):
+    """Both forms stop at a stationary point of the same chi^2 from the same
+    start; on noisy stamps they agree where both converge, and the full
+    gradient vanishes there."""
+    b = synth.make("plain32" if mask == 0xF0 else "plain48", count=12)
+    agree = 0
+    for s in range(b.n):
+        img = b.stamp(s)
+        sg = float(b.sigma[s])
+        side = img.shape[0]
+        t = b.truth[s]
+        p0 = t * np.array([1, 1, 1, 1, 1.2, 0.9, 1, 1]) + np.array([0.2, -0.1, 0, 0, 0, 0, 0, 0])
+        p0[5] = 0.5 if mask == 0xF0 else p0[5]
+        o1 = oracle.opts(free_mask=mask, tol_lm=1e-10, max_iter_lm=400)
+        o0 = oracle.opts(free_mask=mask, tol_lm=1e-10, max_iter_lm=400, linear_init=0)
+        r1 = oracle.fit(img, sg, p0, o=o1)
+        r0 = oracle.fit(img, sg, p0, o=o0)
+        if not (r1["status"] & r0["status"] & oracle.CONVERGED):
+            continue
+        scl = np.array([1, 1, 1, 1, r1["p"][4], r1["p"][5], abs(r1["p"][6]), sg])
+        if np.max(np.abs(r1["p"] - r0["p"]) / scl) < 1e-6:
+            agree += 1
+        _, g, _ = oracle.chi2(img, sg, r0["p"], want_grad=True)
+        free = [k for k in range(8) if mask >> k & 1]
+        assert np.max(np.abs(g[free] * scl[free])) < 1e-5 * max(r0["chi2"], 1.0)
+    assert agree >= 8

@@ -42,6 +42,9 @@ FLOP_PER_PIXEL_SWEEP = 140.0
 FLOP_PER_PIXEL_CENTROID = 14.0
 FLOP_PER_PIXEL_MOMENTS = 35.0
 FLOP_PER_PIXEL_STAR_MOFFAT = 11.0
+# The 4-parameter sweep (Re, n free, I0 and sky columns): model + residual
+# 31, Jacobian columns for Re and n 8, J^T J 15, J^T r and chi^2 9.
+FLOP_PER_PIXEL_SWEEP_4 = 63.0
 # MI355X HBM3E: 8 TB/s.
 HBM_PEAK_GBS = 8000.0
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s; one
@@ -116,11 +119,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
-    ap.add_argument("--workload", default="sersic64h", choices=["sersic64h", "uneven", "stars32", "frames512"],
+    ap.add_argument("--workload", default="sersic64h", choices=["sersic64h", "uneven", "stars32", "frames512", "plain32x"],
                     help="uneven: 1,000,000 stamps of side 16-128 (80%% Sersic, 20%% Moffat), "
                          "fused fit vs autotuned work queue; stars32: 1,048,576 32x32 Moffat "
                          "stars, sizes from weighted moments; frames512: 4,096 512x512 frames, "
-                         "detection and 6 r50 cut-outs")
+                         "detection and 6 r50 cut-outs; plain32x: 262,144 32x32 Gaussian "
+                         "galaxies, 4-parameter fit profiled vs unprofiled")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -140,6 +144,8 @@ def main():
         return bench_stars(args)
     if args.workload == "frames512":
         return bench_frames(args)
+    if args.workload == "plain32x":
+        return bench_profiled(args)
     forms = [f for f in args.forms.split(",") if f]
     # Stamps are generated (in worker processes) before this process touches
     # the GPU, so no worker is forked from a process with an initialised runtime.
@@ -463,6 +469,103 @@ def bench_stars(args):
                           "max_rel_beta": float(rel[:, 1].max()) if both.any() else None,
                           "max_rel_i0": float(rel[:, 2].max()) if both.any() else None,
                           "within_1e-3": float((rel.max(1) <= 1e-3).mean()) if both.any() else None}
+    print(json.dumps(line), flush=True)
+
+
+def bench_profiled(args):
+    """The paper's split on the 32x32 Gaussian galaxies of the first benchmark
+    configuration: centre and ellipticity from the moments, then (Re, n)
+    searched with (I0, sky) profiled at every evaluation (linear_init 1), or
+    all four searched by the same LM (linear_init 0)."""
+    import numpy as np
+
+    import synth
+
+    t = time.time()
+    b = synth.make("plain32x", count=args.count)
+    log("generated %d stamps (32x32) in %.1f s" % (b.n, time.time() - t))
+
+    import torch
+
+    import paper_1203_0571_amd as shape
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    db = shape.DeviceBatch.from_host(b, dev)
+    forms = {"profiled": shape.default_opts(free_mask=shape.MASK_SIZE),
+             "unprofiled": shape.default_opts(free_mask=shape.MASK_SIZE, linear_init=0)}
+
+    def step(o, ev=None):
+        r0, _, _ = shape.centroid(db, o)
+        r1, _, _ = shape.moments(db, r0, o)
+        if ev:
+            ev[0].record()
+        fit = shape.fit_sersic(db, rec=r1, opts=o)
+        if ev:
+            ev[1].record()
+        return fit
+
+    res = {}
+    for name, o in forms.items():
+        for _ in range(args.warmup):
+            step(o)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            fit = step(o, evs[k])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = fit["status"].cpu().numpy()
+        sw = fit["sweeps"].cpu().numpy().astype(np.float64)
+        res[name] = dict(fit=fit, objs=b.n * args.steps / el, ms=el / args.steps * 1e3,
+                         fit_ms=float(np.mean([x.elapsed_time(y) for x, y in evs])),
+                         conv=float(((st & shape.ST_CONVERGED) != 0).mean()),
+                         mean_trials=float(fit["iters"].float().mean().item()),
+                         mean_sweeps=float(sw.mean()), px_sweeps=float(sw.sum()) * 32 * 32)
+        log("%-10s %.0f objects/s, fit %.3f ms, %.2f trials, converged %.4f"
+            % (name, res[name]["objs"], res[name]["fit_ms"], res[name]["mean_trials"],
+               res[name]["conv"]))
+    r = res["profiled"]
+    achieved = r["px_sweeps"] * FLOP_PER_PIXEL_SWEEP_4 / (r["fit_ms"] * 1e-3) / 1e12
+    line = {"metric": "objects fitted/sec (32x32 Gaussian galaxies, (Re, n, I0, sky) fit)",
+            "value": round(r["objs"], 1), "unit": "objects/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms"], 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "plain32x: %d x 32x32 Gaussian galaxies, seed 0" % b.n,
+                       "chosen_form": "profiled",
+                       "forms": {k: {q: round(v, 4) for q, v in x.items() if q != "fit"}
+                                 for k, x in res.items()}},
+            "roofline": {"bound": "alu", "kernel": "fit (profiled, 4 parameters)",
+                         "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                         "traffic": None, "launch_ms": round(r["fit_ms"], 4),
+                         "flop_per_pixel_sweep": FLOP_PER_PIXEL_SWEEP_4}}
+    if not args.no_cpu:
+        import oracle
+        m = min(args.cpu_sample, b.n)
+        sub = b.head(m)
+        par = {}
+        for name, li in (("profiled", 1), ("unprofiled", 0)):
+            o = oracle.opts(free_mask=0xF0, linear_init=li)
+            t = time.perf_counter()
+            ref = oracle.pipeline(sub, o)
+            cpu_s = time.perf_counter() - t
+            if name == "profiled":
+                line["cpu_baseline"] = {"value": round(m / cpu_s, 2), "unit": "objects/s",
+                                        "cores": int(ref["threads"]), "kind": "oracle",
+                                        "sample": "first %d stamps, FP64 oracle, LM tol 1e-9, "
+                                                  "cap 200, %.1f s" % (m, cpu_s)}
+            g = {k: v[:m].cpu().numpy() for k, v in res[name]["fit"].items() if hasattr(v, "cpu")}
+            both = ((g["status"] & shape.ST_CONVERGED) != 0) & ((ref["status"][:, 2] & 1) != 0)
+            rel = np.abs(g["p"][both, 4:6] / ref["p"][both, 4:6] - 1)
+            par[name] = {"sample": m, "both_converged": int(both.sum()),
+                         "max_rel_re": float(rel[:, 0].max()), "max_rel_n": float(rel[:, 1].max()),
+                         "within_bars": float((rel.max(1) <= BARS["rel"]).mean()),
+                         "oracle_mean_trials": float(ref["iters"][:, 2].mean())}
+        line["parity"] = par
     print(json.dumps(line), flush=True)
 
 

@@ -110,7 +110,11 @@ typedef struct {
   double   chi2_rtol;         /* accept a trial if chi2' <= chi2 (1 + rtol) (1e-6) */
   double   n0;                /* starting Sersic index (1) */
   double   moffat_beta;       /* fixed Moffat index (3) */
-  int32_t  linear_init;       /* 1: solve free (I0, sky) linearly at every point */
+  int32_t  linear_init;       /* 1: profile the free (I0, sky) at every evaluated shape
+                                 (the paper's split, Sec. 4.1; default); 0: search them
+                                 with the shape by the same LM from their linear optimum
+                                 at the start (shape_fit_sersic with free_mask 0xF0 and
+                                 no model array only, else SHAPE_EUNSUPPORTED) */
   int32_t  reserved;
 } shape_opts;
 

@@ -143,7 +143,8 @@ int shape_fit_sersic(const shape_batch* b, const shape_opts* o, const float* p_i
   if (rc == SHAPE_OK) rc = check_opts(o);
   if (rc != SHAPE_OK) return rc;
   if (o->free_mask != 0xFFu && o->free_mask != 0xF0u) return SHAPE_EUNSUPPORTED;
-  if (!o->linear_init) return SHAPE_EUNSUPPORTED;
+  // the unprofiled form exists for the 4-parameter Sersic fit only
+  if (!o->linear_init && (o->free_mask != 0xF0u || b->model)) return SHAPE_EUNSUPPORTED;
   if (b->n == 0) return SHAPE_OK;
   if ((!p_init && !rec) || !p_out || !chi2 || !iters || !status) return SHAPE_EINVAL;
   return from_hip(launch_fit(*b, kopts(o), p_init, rec, p_out, chi2, perr, iters, status,

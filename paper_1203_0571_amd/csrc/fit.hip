@@ -14,7 +14,7 @@ namespace {
 #ifndef SHAPE_FIT_WAVES_PER_SIMD
 #define SHAPE_FIT_WAVES_PER_SIMD 4
 #endif
-template <int DT, int MODEL, uint32_t MASK, int LAYOUT>
+template <int DT, int MODEL, uint32_t MASK, int LAYOUT, bool PROF = true>
 __global__ __launch_bounds__(kWave, SHAPE_FIT_WAVES_PER_SIMD) void fit_kernel(
     shape_batch b, KOpts o, const float* p_init, const float* rec, float* p_out, float* chi2,
     float* perr, int32_t* iters, uint32_t* status, int32_t* sweeps) {
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kWave, SHAPE_FIT_WAVES_PER_SIMD) void fit_kernel(
     }
     lm_start<DT, MODEL, MASK, 1, LAYOUT>(b, o, st, p_init, rec, s, W, nullptr, tid);
     while (!W.L.done && W.L.it < o.max_iter_lm)
-      lm_iterate<DT, MODEL, MASK, 1, LAYOUT>(b, o, st, W, nullptr, tid);
+      lm_iterate<DT, MODEL, MASK, 1, LAYOUT, PROF>(b, o, st, W, nullptr, tid);
     lm_finish<MODEL, MASK>(o, st, W.L, W.sums[W.cur], s, p_out, chi2, perr, iters, status, sweeps,
                            tid);
     __syncthreads();  // W is reused by the next stamp of this wave
@@ -54,7 +54,16 @@ void launch_fit_model(const shape_batch& b, const KOpts& o, const float* p_init,
   const dim3 g((unsigned)grid), t(kWave);
   // A batch of one side that divides 64 (no side array) takes the row layout.
   const bool rows = MODEL == SHAPE_SERSIC && !b.side && !b.model && rows_layout_fits(b.side0);
-  if (o.free_mask == kMaskAll) {
+  if (!o.linear_init) {
+    // the unprofiled form: Sersic, (Re, n, I0, sky) free (checked by the caller)
+    if constexpr (MODEL != SHAPE_SERSIC) return;
+    if (rows)
+      hipLaunchKernelGGL((fit_kernel<DT, SHAPE_SERSIC, kMaskSize, kLayoutRows, false>), g, t, 0,
+                         stream, b, o, p_init, rec, p_out, chi2, perr, iters, status, sweeps);
+    else
+      hipLaunchKernelGGL((fit_kernel<DT, SHAPE_SERSIC, kMaskSize, kLayoutAny, false>), g, t, 0,
+                         stream, b, o, p_init, rec, p_out, chi2, perr, iters, status, sweeps);
+  } else if (o.free_mask == kMaskAll) {
     if (rows)
       hipLaunchKernelGGL((fit_kernel<DT, MODEL, kMaskAll, kLayoutRows>), g, t, 0, stream, b, o,
                          p_init, rec, p_out, chi2, perr, iters, status, sweeps);

@@ -271,12 +271,16 @@ __device__ __forceinline__ void lm_start(const shape_batch& b, const KOpts& o, c
 // One LM trial from the current sums; the trial's sums go to the other buffer
 // and become current when the trial is accepted.  Sets W.L.done when the fit
 // has converged or stalled; the caller enforces max_iter_lm.
-template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT = kLayoutAny>
+// PROF = false: the unprofiled form, the free amplitudes are searched by the
+// same damped step as the shape parameters (no Schur complement, no
+// amplitude update at the trial), with s_6 = |I0| and s_7 = sigma in the
+// stopping rule.
+template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT = kLayoutAny, bool PROF = true>
 __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o, const Stamp& st,
                                            LmShared& W, double* xs, int tid) {
   constexpr uint32_t EM = eff_mask(MASK, MODEL);
-  constexpr uint32_t LIN = EM & 0xC0u;
-  constexpr uint32_t NL = EM & 0x3Fu;  // free shape parameters
+  constexpr uint32_t LIN = PROF ? (EM & 0xC0u) : 0u;  // profiled amplitudes
+  constexpr uint32_t NL = PROF ? (EM & 0x3Fu) : EM;   // parameters of the damped step
   constexpr int NN = popcount(NL);
   const int cur = W.cur;
   // Phase 1a: the damped Schur complement of the amplitude block, one lower-
@@ -336,7 +340,8 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
       double pt[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) pt[k] = L.p[k];
-      const double iscl[6] = {1.0, 1.0, 1.0, 1.0, 1.0 / L.p[4], 1.0 / L.p[5]};
+      const double iscl[8] = {1.0, 1.0, 1.0, 1.0, 1.0 / L.p[4], 1.0 / L.p[5],
+                              1.0 / fabs(L.p[6]), 1.0 / st.sigma};
 #pragma unroll
       for (int a = 0; a < NN; ++a) {
         pt[nth_bit(NL, a)] += x[a];

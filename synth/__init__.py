@@ -72,6 +72,9 @@ class Workload:
 WORKLOADS = {
     "plain32": Workload("plain32", 1_000, 32, "gauss32",
                         description="1,000 x 32x32 FP32 elliptical Gaussian galaxies, 4-parameter fit"),
+    "plain32x": Workload("plain32x", 262_144, 32, "gauss32",
+                         description="262,144 x 32x32 FP32 elliptical Gaussian galaxies drawn as "
+                                     "plain32 (its first 1,000 stamps are plain32)"),
     "plain48": Workload("plain48", 100_000, 48, "sersic",
                         description="100,000 x 48x48 FP32 Sersic galaxies, 8-parameter fit"),
     "uneven": Workload("uneven", 1_000_000, None, "uneven",

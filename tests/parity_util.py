@@ -26,7 +26,7 @@ def oracle_opts_like(gpu_opts, **kw):
                     k_gain=gpu_opts.k_gain, tol_x=gpu_opts.tol_x, tol_g=gpu_opts.tol_g,
                     gmax=gpu_opts.gmax, lambda0=gpu_opts.lambda0, chi2_rtol=gpu_opts.chi2_rtol,
                     n0=gpu_opts.n0, moffat_beta=gpu_opts.moffat_beta,
-                    free_mask=gpu_opts.free_mask)
+                    free_mask=gpu_opts.free_mask, linear_init=gpu_opts.linear_init)
     for k, v in kw.items():
         setattr(o, k, v)
     return o

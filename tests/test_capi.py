@@ -217,3 +217,16 @@ def test_frame_argument_errors(shape):
     e = _frames(shape, n=0, pixels=None)
     assert L.shape_frame_detect(C.byref(e), 128, None, None, None, None, None) == shape.OK
     assert L.shape_frame_cut(C.byref(e), None, None, None, None, None) == shape.OK
+
+
+def test_unprofiled_form_is_limited_to_the_4_parameter_sersic_fit(shape):
+    L = shape.lib
+    out = C.c_void_p(0x3000)
+    b = _batch(shape)
+    o = shape.default_opts(linear_init=0)          # all eight free: not provided
+    assert L.shape_fit_sersic(C.byref(b), C.byref(o), out, None, out, out, None, out, out, None,
+                              None) == shape.EUNSUPPORTED
+    bm = _batch(shape, model=0x5000)
+    o = shape.default_opts(linear_init=0, free_mask=shape.MASK_SIZE)
+    assert L.shape_fit_sersic(C.byref(bm), C.byref(o), out, None, out, out, None, out, out, None,
+                              None) == shape.EUNSUPPORTED

@@ -43,6 +43,24 @@ def test_gaussian_workload_4_params(shape):
     np.testing.assert_array_equal(g["p"][conv, :4], g["moments"][conv, :4])
 
 
+def test_unprofiled_4_params(shape):
+    """The unprofiled form (linear_init = 0: I0 and sky searched with Re and n
+    by the same LM) against the oracle's unprofiled form; it reaches the
+    profiled fit's minimum in more trials."""
+    b = synth.make("plain32", count=512)
+    o = shape.default_opts(free_mask=shape.MASK_SIZE, linear_init=0)
+    g = run_gpu(shape, b, o)
+    ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
+    r = compare(g, ref, 0xF0, "plain32 unprofiled")
+    _check_bars(r, 0.95)
+    gp = run_gpu(shape, b, shape.default_opts(free_mask=shape.MASK_SIZE))
+    both = ((g["status"][:, 2] & gp["status"][:, 2] & shape.ST_CONVERGED) != 0)
+    assert both.mean() > 0.95
+    rel = np.abs(g["p"][both, 4:6] / gp["p"][both, 4:6] - 1)
+    assert rel.max() <= BAR_REL
+    assert g["iters"][both, 2].mean() > gp["iters"][both, 2].mean()
+
+
 @pytest.mark.parametrize("workload,count", [("plain48", 2048), ("sersic64", 1024)])
 def test_sersic_workloads_8_params(shape, workload, count):
     b = synth.make(workload, count=count)

@@ -545,7 +545,7 @@ def bench_profiled(args):
                          "flop_per_pixel_sweep": FLOP_PER_PIXEL_SWEEP_4}}
     if not args.no_cpu:
         import oracle
-        m = min(args.cpu_sample, b.n)
+        m = min(args.cpu_sample * 16, b.n)   # 32x32 stamps fit fast: ~15 s of oracle work
         sub = b.head(m)
         par = {}
         for name, li in (("profiled", 1), ("unprofiled", 0)):

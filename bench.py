@@ -53,22 +53,34 @@ ALU_PEAK_TFLOPS = 78.6
 BARS = dict(x=1e-3, e=1e-4, rel=1e-3)
 
 
-# Sources that make up the fit kernel; the HBM counters in profiles/ are used
-# only while these are unchanged.
+# Sources that make up the fit kernel and the frame detection; the HBM
+# counters in profiles/ are used only while these are unchanged.
 FIT_SOURCES = ["paper_1203_0571_amd/csrc/fit.hip", "paper_1203_0571_amd/csrc/lm.hpp",
                "paper_1203_0571_amd/csrc/sweep.hpp", "paper_1203_0571_amd/csrc/common.hpp",
                "paper_1203_0571_amd/csrc/bn_table.h", "paper_1203_0571_amd/csrc/kernels.hpp",
                "include/shape.h", "paper_1203_0571_amd/build.py"]
+FRAME_SOURCES = ["paper_1203_0571_amd/csrc/frames.hip", "paper_1203_0571_amd/csrc/common.hpp",
+                 "paper_1203_0571_amd/csrc/bn_table.h", "paper_1203_0571_amd/csrc/kernels.hpp",
+                 "include/shape.h", "paper_1203_0571_amd/build.py"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fit_sersic64h_hbm_traffic.md")
+FRAME_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "frame_detect_frames512_hbm_traffic.md")
 
 
-def fit_traffic_bytes():
-    """HBM bytes per launch of the FP16 fit from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE in KiB, each scaled by its copy calibration),
-    or None if the summary is missing or the kernel's sources changed since."""
+def sources_hash(files):
     import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(path, files, form=""):
+    """HBM bytes per launch from a committed counter summary (FETCH_SIZE and
+    WRITE_SIZE in KiB, each scaled by its copy calibration), or None if the
+    summary is missing or the kernel's sources changed since it was taken."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     kv = {}
@@ -76,14 +88,18 @@ def fit_traffic_bytes():
         if ":" in line and line.startswith("    "):
             k, v = line.strip().split(":", 1)
             kv[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for f in FIT_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if kv.get("source_sha256_16") != h.hexdigest()[:16]:
+    if kv.get("source_sha256_16") != sources_hash(files):
         return None
-    return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
-            float(kv["write_kib"]) * float(kv["write_scale"])) * 1024.0
+    sfx = "_" + form if form else ""
+    if "fetch_kib" + sfx not in kv:
+        return None
+    return (float(kv["fetch_kib" + sfx]) * float(kv["fetch_scale"]) +
+            float(kv["write_kib" + sfx]) * float(kv["write_scale"])) * 1024.0
+
+
+def fit_traffic_bytes(form):
+    """HBM bytes per launch of the fused fit for form "plain" or "f16"."""
+    return counter_traffic(TRAFFIC_FILE, FIT_SOURCES, form)
 
 
 def log(*a):
@@ -289,7 +305,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "fit (" + chosen + ")",
                      "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                     "traffic": fit_traffic_bytes() if chosen == "f16" else None,
+                     "traffic": fit_traffic_bytes(chosen) if chosen in ("plain", "f16") else None,
                      "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "launch_ms": round(rc["fit_ms"], 4),
                      "flop_per_pixel_sweep": FLOP_PER_PIXEL_SWEEP,
@@ -635,7 +651,10 @@ def bench_frames(args):
                        "nonpositive_flux_frames": int(((st & shape.ST_NONPOSITIVE_FLUX) != 0).sum())},
             "roofline": {"bound": "hbm", "kernel": "frame detect", "achieved": round(achieved, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": counter_traffic(FRAME_TRAFFIC_FILE, FRAME_SOURCES),
+                         "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, "
+                                         "copy-calibrated)",
                          "launch_ms": round(det_ms, 4), "bytes_per_launch": det_bytes}}
     if not args.no_cpu:
         import oracle

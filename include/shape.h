@@ -316,11 +316,13 @@ int shape_frame_offsets(const int32_t* box, int64_t n, int64_t* offset, int64_t*
                         void* stream);
 
 /* Copy every box of every frame into stamps (FP32, F16 frames dequantised)
- * at offset[i]; sides [n] (optional, may be NULL) receives each side, so
- * (stamps, offset, sides) form a shape_batch.  Boxes must lie inside their
- * frames (as shape_frame_detect makes them); side 0 copies nothing. */
+ * at offset[i]; stamps holds capacity floats (device).  sides [n] (optional,
+ * may be NULL) receives each side, so (stamps, offset, sides) form a
+ * shape_batch.  A box that does not lie inside its frame, or whose cut-out
+ * would pass the capacity, copies nothing and gets side 0 (such a stamp is
+ * then flagged BAD_INPUT by the stamp calls). */
 int shape_frame_cut(const shape_frames* frames, const int32_t* box, const int64_t* offset,
-                    float* stamps, int32_t* sides, void* stream);
+                    float* stamps, int64_t capacity, int32_t* sides, void* stream);
 
 #ifdef __cplusplus
 }

@@ -127,7 +127,7 @@ def _load():
     fp = C.POINTER(ShapeFrames)
     lib.shape_frame_detect.argtypes = [fp, C.c_int32, vp, vp, vp, vp, vp]
     lib.shape_frame_offsets.argtypes = [vp, C.c_int64, vp, vp, vp]
-    lib.shape_frame_cut.argtypes = [fp, vp, vp, vp, vp, vp]
+    lib.shape_frame_cut.argtypes = [fp, vp, vp, vp, C.c_int64, vp, vp]
     for f in ("shape_frame_detect", "shape_frame_offsets", "shape_frame_cut"):
         getattr(lib, f).restype = C.c_int
     qp = C.POINTER(QueueCfg)
@@ -400,8 +400,8 @@ def frame_cut(frames: DeviceFrames, box: torch.Tensor, sigma: torch.Tensor,
         stamps, total = out, out.numel()
     sides = torch.empty(n, dtype=torch.int32, device=dev)
     f = frames.c_struct()
-    _check(lib.shape_frame_cut(C.byref(f), _ptr(box), _ptr(off), _ptr(stamps), _ptr(sides),
-                               _stream(dev)), "shape_frame_cut")
+    _check(lib.shape_frame_cut(C.byref(f), _ptr(box), _ptr(off), _ptr(stamps), stamps.numel(),
+                               _ptr(sides), _stream(dev)), "shape_frame_cut")
     return DeviceBatch(pixels=stamps[:total] if total else stamps[:0], sigma=sigma, offsets=off,
                        sides=sides)
 

@@ -207,12 +207,14 @@ int shape_frame_offsets(const int32_t* box, int64_t n, int64_t* offset, int64_t*
 }
 
 int shape_frame_cut(const shape_frames* f, const int32_t* box, const int64_t* offset,
-                    float* stamps, int32_t* sides, void* stream) {
+                    float* stamps, int64_t capacity, int32_t* sides, void* stream) {
   int rc = check_frames(f);
   if (rc != SHAPE_OK) return rc;
+  if (capacity < 0) return SHAPE_EINVAL;
   if (f->n == 0) return SHAPE_OK;
   if (!box || !offset || !stamps) return SHAPE_EINVAL;
-  return from_hip(launch_frame_cut(*f, box, offset, stamps, sides, (hipStream_t)stream));
+  return from_hip(
+      launch_frame_cut(*f, box, offset, stamps, capacity, sides, (hipStream_t)stream));
 }
 
 int shape_queue_default_cfg(shape_queue_cfg* c) {

@@ -304,18 +304,25 @@ __global__ __launch_bounds__(1024) void offsets_kernel(const int32_t* box, int64
 }
 
 // Copy each box into the packed stamps (FP32), one workgroup per frame.
+// A box outside its frame, or whose cut-out would not fit in the capacity,
+// copies nothing and gets side 0 (its stamp is then rejected downstream).
 template <int DT>
 __global__ __launch_bounds__(kFrameThreads) void cut_kernel(shape_frames f, const int32_t* box,
                                                             const int64_t* offset, float* stamps,
-                                                            int32_t* sides) {
+                                                            int64_t capacity, int32_t* sides) {
   const int W = f.width;
   const int64_t npix = (int64_t)f.height * W;
   for (int64_t fr = blockIdx.x; fr < f.n; fr += gridDim.x) {
-    const int ox = box[fr * 3 + 0], oy = box[fr * 3 + 1], s = box[fr * 3 + 2];
+    const int ox = box[fr * 3 + 0], oy = box[fr * 3 + 1];
+    int s = box[fr * 3 + 2];
+    const int64_t o0 = offset[fr];
+    const bool fits = s > 0 && ox >= 0 && oy >= 0 && ox <= W - s && oy <= f.height - s &&
+                      o0 >= 0 && o0 <= capacity - (int64_t)s * s;
+    if (!fits) s = 0;
     if (threadIdx.x == 0 && sides) sides[fr] = s;
-    if (s <= 0) continue;
+    if (s == 0) continue;
     const float scale = (DT == SHAPE_F16_SCALED) ? f.scale[fr] : 1.0f;
-    const int64_t base = fr * npix + (int64_t)oy * W + ox, o = offset[fr];
+    const int64_t base = fr * npix + (int64_t)oy * W + ox, o = o0;
     const int n = s * s;
     for (int q = threadIdx.x; q < n; q += kFrameThreads) {
       const int i = q / s, j = q - i * s;
@@ -356,14 +363,14 @@ hipError_t launch_frame_offsets(const int32_t* box, int64_t n, int64_t* offset, 
 }
 
 hipError_t launch_frame_cut(const shape_frames& f, const int32_t* box, const int64_t* offset,
-                            float* stamps, int32_t* sides, hipStream_t stream) {
+                            float* stamps, int64_t capacity, int32_t* sides, hipStream_t stream) {
   const int64_t grid = f.n < (1ll << 30) ? f.n : (1ll << 30);
   if (f.dtype == SHAPE_F32)
     hipLaunchKernelGGL(cut_kernel<SHAPE_F32>, dim3((unsigned)grid), dim3(kFrameThreads), 0,
-                       stream, f, box, offset, stamps, sides);
+                       stream, f, box, offset, stamps, capacity, sides);
   else
     hipLaunchKernelGGL(cut_kernel<SHAPE_F16_SCALED>, dim3((unsigned)grid), dim3(kFrameThreads), 0,
-                       stream, f, box, offset, stamps, sides);
+                       stream, f, box, offset, stamps, capacity, sides);
   return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ hipError_t launch_frame_detect(const shape_frames& f, int max_side, float* info,
 hipError_t launch_frame_offsets(const int32_t* box, int64_t n, int64_t* offset, int64_t* total,
                                 hipStream_t stream);
 hipError_t launch_frame_cut(const shape_frames& f, const int32_t* box, const int64_t* offset,
-                            float* stamps, int32_t* sides, hipStream_t stream);
+                            float* stamps, int64_t capacity, int32_t* sides, hipStream_t stream);
 
 hipError_t launch_chi2(const shape_batch& b, const float* params, const float* grad_chi2,
                        float* chi2, float* grad_p, float* jtj, float* jtr, bool grad,

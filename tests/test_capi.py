@@ -202,21 +202,22 @@ def test_frame_argument_errors(shape):
                 dict(dtype=shape.F16_SCALED)]:
         f = _frames(shape, **bad)
         assert L.shape_frame_detect(C.byref(f), 128, out, out, out, out, None) == shape.EINVAL
-        assert L.shape_frame_cut(C.byref(f), out, out, out, None, None) == shape.EINVAL
+        assert L.shape_frame_cut(C.byref(f), out, out, out, 100, None, None) == shape.EINVAL
     f = _frames(shape)
     assert L.shape_frame_detect(None, 128, out, out, out, out, None) == shape.EINVAL
     for ms in (3, 129):
         assert L.shape_frame_detect(C.byref(f), ms, out, out, out, out, None) == shape.EINVAL
     assert L.shape_frame_detect(C.byref(f), 128, None, out, out, out, None) == shape.EINVAL
     assert L.shape_frame_detect(C.byref(f), 128, out, out, None, out, None) == shape.EINVAL
-    assert L.shape_frame_cut(C.byref(f), None, out, out, None, None) == shape.EINVAL
-    assert L.shape_frame_cut(C.byref(f), out, out, None, None, None) == shape.EINVAL
+    assert L.shape_frame_cut(C.byref(f), None, out, out, 100, None, None) == shape.EINVAL
+    assert L.shape_frame_cut(C.byref(f), out, out, None, 100, None, None) == shape.EINVAL
+    assert L.shape_frame_cut(C.byref(f), out, out, out, -1, None, None) == shape.EINVAL
     assert L.shape_frame_offsets(out, -1, out, out, None) == shape.EINVAL
     assert L.shape_frame_offsets(out, 3, out, None, None) == shape.EINVAL
     assert L.shape_frame_offsets(None, 3, out, out, None) == shape.EINVAL
     e = _frames(shape, n=0, pixels=None)
     assert L.shape_frame_detect(C.byref(e), 128, None, None, None, None, None) == shape.OK
-    assert L.shape_frame_cut(C.byref(e), None, None, None, None, None) == shape.OK
+    assert L.shape_frame_cut(C.byref(e), None, None, None, 0, None, None) == shape.OK
 
 
 def test_unprofiled_form_is_limited_to_the_4_parameter_sersic_fit(shape):

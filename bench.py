@@ -135,12 +135,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
-    ap.add_argument("--workload", default="sersic64h", choices=["sersic64h", "uneven", "stars32", "frames512", "plain32x"],
+    ap.add_argument("--workload", default="sersic64h", choices=["sersic64h", "uneven", "stars32", "frames512", "plain32x",
+                             "sersic64"],
                     help="uneven: 1,000,000 stamps of side 16-128 (80%% Sersic, 20%% Moffat), "
                          "fused fit vs autotuned work queue; stars32: 1,048,576 32x32 Moffat "
                          "stars, sizes from weighted moments; frames512: 4,096 512x512 frames, "
                          "detection and 6 r50 cut-outs; plain32x: 262,144 32x32 Gaussian "
-                         "galaxies, 4-parameter fit profiled vs unprofiled")
+                         "galaxies, 4-parameter fit profiled vs unprofiled; sersic64: 65,536 "
+                         "64x64 stamps, chi^2 forward and adjoint gradient")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -162,6 +164,8 @@ def main():
         return bench_frames(args)
     if args.workload == "plain32x":
         return bench_profiled(args)
+    if args.workload == "sersic64":
+        return bench_adjoint(args)
     forms = [f for f in args.forms.split(",") if f]
     # Stamps are generated (in worker processes) before this process touches
     # the GPU, so no worker is forked from a process with an initialised runtime.
@@ -582,6 +586,89 @@ def bench_profiled(args):
                          "within_bars": float((rel.max(1) <= BARS["rel"]).mean()),
                          "oracle_mean_trials": float(ref["iters"][:, 2].mean())}
         line["parity"] = par
+    print(json.dumps(line), flush=True)
+
+
+def bench_adjoint(args):
+    """chi^2 and its adjoint gradient (the FP64 instance of the sweep) on the
+    65,536 64x64 Sersic stamps, at parameters away from the optimum; also the
+    gradient through torch.autograd (SersicChi2)."""
+    import numpy as np
+
+    import synth
+
+    t = time.time()
+    b = synth.make("sersic64", count=args.count)
+    log("generated %d stamps (64x64) in %.1f s" % (b.n, time.time() - t))
+    rng = np.random.default_rng(42)
+    p = b.truth.copy()
+    p[:, 0:2] += rng.uniform(-0.3, 0.3, (b.n, 2))
+    p[:, 4] *= rng.uniform(0.85, 1.15, b.n)
+    p[:, 5] *= rng.uniform(0.85, 1.15, b.n)
+
+    import torch
+
+    import paper_1203_0571_amd as shape
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    db = shape.DeviceBatch.from_host(b, dev)
+    pt = torch.from_numpy(p.astype(np.float32)).to(dev)
+    calls = {"forward": lambda: shape.chi2_fwd(db, pt),
+             "backward": lambda: shape.chi2_bwd(db, pt),
+             "backward_jtj": lambda: shape.chi2_bwd(db, pt, want_normal=True)}
+    ms = {}
+    for name, fn in calls.items():
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms[name] = e0.elapsed_time(e1) / args.steps
+    q = pt.clone().requires_grad_(True)
+    for _ in range(args.warmup):
+        shape.sersic_chi2(q, db).sum().backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        q.grad = None
+        shape.sersic_chi2(q, db).sum().backward()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    log("adjoint: %s ms per launch; autograd forward+backward %.3f ms"
+        % ({k: round(v, 3) for k, v in ms.items()}, el / args.steps * 1e3))
+    # the algorithm's 140 FLOP per pixel (transcendentals counted once, as in
+    # the fit) against the FP64 vector peak: the series for log2 / exp2 are
+    # what this instance spends beyond them
+    achieved = b.n * 64 * 64 * FLOP_PER_PIXEL_SWEEP / (ms["backward"] * 1e-3) / 1e12
+    line = {"metric": "chi^2 gradients/sec (64x64 Sersic stamps, adjoint)",
+            "value": round(b.n * args.steps / el, 1), "unit": "gradients/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(el / args.steps * 1e3, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "sersic64: %d x 64x64 Sersic stamps, seed 0" % b.n,
+                       "kernel_ms": {k: round(v, 4) for k, v in ms.items()},
+                       "note": "value = forward + backward through torch.autograd"},
+            "roofline": {"bound": "alu", "kernel": "chi2 backward (FP64)",
+                         "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                         "traffic": None, "launch_ms": round(ms["backward"], 4)}}
+    if not args.no_cpu:
+        import oracle
+        m = min(2048, b.n)
+        t = time.perf_counter()
+        for s_ in range(m):
+            oracle.chi2(b.stamp(s_), float(b.sigma[s_]), p[s_].astype(np.float32).astype(np.float64),
+                        want_grad=True)
+        cpu_s = time.perf_counter() - t
+        line["cpu_baseline"] = {"value": round(m / cpu_s, 2), "unit": "gradients/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": "first %d stamps, FP64 oracle chi^2 + gradient + J^T J, "
+                                          "one thread, %.1f s" % (m, cpu_s)}
     print(json.dumps(line), flush=True)
 
 

@@ -124,9 +124,9 @@ __global__ __launch_bounds__(kFrameThreads) void detect_kernel(shape_frames f, i
       amax = fmax(amax, fabs(d));
     };
     if (vec4) {
-      // four pixels per load (16 B FP32 / 8 B FP16), two loads in flight
+      // four pixels per load (16 B FP32 / 8 B FP16), four loads in flight
       const int64_t n4 = npix >> 2;
-#pragma unroll 2
+#pragma unroll 4
       for (int64_t q = tid; q < n4; q += kFrameThreads) {
         float v[4];
         load4<DT>(f, base, q * 4, scale, v);

@@ -50,14 +50,18 @@ __device__ __forceinline__ double log2_f64(double x) {
   return (double)e + 2.0 * z * s * kLog2e;
 }
 
+// 1 / n! for the Taylor series of e^y (formed at compile time).
+constexpr double inv_factorial(int n) { return n <= 1 ? 1.0 : inv_factorial(n - 1) / n; }
+
 __device__ __forceinline__ double exp2_f64(double x) {
   if (!(x > -1100.0)) return x != x ? x : 0.0;
   if (x > 1100.0) return __builtin_inf();
   const double k = __builtin_rint(x);
   const double y = (x - k) * kLn2;
-  double s = 1.0;
+  // sum_{n <= 13} y^n / n! by Horner
+  double s = inv_factorial(13);
 #pragma unroll
-  for (int n = 13; n >= 1; --n) s = fma(s, y / (double)n, 1.0);
+  for (int n = 12; n >= 0; --n) s = fma(s, y, inv_factorial(n));
   return __builtin_ldexp(s, (int)k);
 }
 

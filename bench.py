@@ -266,6 +266,17 @@ def main():
                        "cores": int(refs["f32"]["threads"]), "kind": "oracle",
                        "sample": "first %d stamps of the workload (FP32), FP64 oracle, "
                                  "LM tol 1e-9, cap 200, %.1f s" % (m, cpu_s)}
+        if cpu is not None:
+            # the same oracle on one thread, comparable with the paper's
+            # single-core timings (0.1 s centroid + ellipticity, 0.5 s fit per
+            # object on a 2.2 GHz CPU, Sec. 4.1)
+            m1 = min(1024, m)
+            t = time.perf_counter()
+            oracle.pipeline((b16 or b32).head(m1), oracle.opts(), threads=1)
+            s1 = time.perf_counter() - t
+            cpu["one_thread"] = {"value": round(m1 / s1, 2), "unit": "objects/s",
+                                 "sample": "first %d stamps, %.1f s" % (m1, s1)}
+            log("cpu oracle, one thread: %d stamps in %.1f s" % (m1, s1))
         for form, r in results.items():
             par[form] = parity(np, shape, oracle, r["fit"], refs["f32" if form == "plain" else "f16"], m)
         if "f16" in refs and "f32" in refs:
@@ -317,6 +328,12 @@ def main():
     }
     if cpu:
         line["cpu_baseline"] = cpu
+    # context, not the target: the paper's single-core timings for this path
+    line["paper_context"] = {"hardware": "single-core 2.2 GHz Intel CPU (Sec. 4.1)",
+                             "seconds_per_object": {"centroid_and_ellipticity": 0.1,
+                                                    "two_parameter_fit": 0.5,
+                                                    "seven_parameter_brute_force": 6.0},
+                             "objects_per_s": round(1.0 / 0.6, 3)}
     if par:
         line["parity"] = par
     print(json.dumps(line), flush=True)

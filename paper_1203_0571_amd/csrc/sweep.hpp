@@ -50,19 +50,30 @@ __device__ __forceinline__ double log2_f64(double x) {
   return (double)e + 2.0 * z * s * kLog2e;
 }
 
-// 1 / n! for the Taylor series of e^y (formed at compile time).
-constexpr double inv_factorial(int n) { return n <= 1 ? 1.0 : inv_factorial(n - 1) / n; }
+// 1 / n! for the Taylor series of e^y, as compile-time constants.
+template <int N>
+struct InvFact {
+  static constexpr double v = InvFact<N - 1>::v / N;
+};
+template <>
+struct InvFact<0> {
+  static constexpr double v = 1.0;
+};
+// sum_{n = M..13} y^(n-M) / n! by Horner (M = 0: the series of e^y).
+template <int M>
+__device__ __forceinline__ double exp_taylor(double y) {
+  if constexpr (M == 13)
+    return InvFact<13>::v;
+  else
+    return fma(exp_taylor<M + 1>(y), y, InvFact<M>::v);
+}
 
 __device__ __forceinline__ double exp2_f64(double x) {
   if (!(x > -1100.0)) return x != x ? x : 0.0;
   if (x > 1100.0) return __builtin_inf();
   const double k = __builtin_rint(x);
   const double y = (x - k) * kLn2;
-  // sum_{n <= 13} y^n / n! by Horner
-  double s = inv_factorial(13);
-#pragma unroll
-  for (int n = 12; n >= 0; --n) s = fma(s, y, inv_factorial(n));
-  return __builtin_ldexp(s, (int)k);
+  return __builtin_ldexp(exp_taylor<0>(y), (int)k);
 }
 
 // Arithmetic of one sweep instance: FP32 with the hardware transcendentals

@@ -14,6 +14,22 @@ namespace {
 #ifndef SHAPE_FIT_WAVES_PER_SIMD
 #define SHAPE_FIT_WAVES_PER_SIMD 4
 #endif
+#ifndef SHAPE_FIT_STAGE_F16
+#define SHAPE_FIT_STAGE_F16 1
+#endif
+template <int DT, int MODEL, uint32_t MASK, int LAYOUT, bool PROF>
+__device__ __forceinline__ void fit_one(const shape_batch& b, const KOpts& o, const Stamp& st,
+                                        const float* p_init, const float* rec, int64_t s,
+                                        LmShared& W, float* p_out, float* chi2, float* perr,
+                                        int32_t* iters, uint32_t* status, int32_t* sweeps,
+                                        int tid) {
+  lm_start<DT, MODEL, MASK, 1, LAYOUT>(b, o, st, p_init, rec, s, W, nullptr, tid);
+  while (!W.L.done && W.L.it < o.max_iter_lm)
+    lm_iterate<DT, MODEL, MASK, 1, LAYOUT, PROF>(b, o, st, W, nullptr, tid);
+  lm_finish<MODEL, MASK>(o, st, W.L, W.sums[W.cur], s, p_out, chi2, perr, iters, status, sweeps,
+                         tid);
+}
+
 template <int DT, int MODEL, uint32_t MASK, int LAYOUT, bool PROF = true>
 __global__ __launch_bounds__(kWave, SHAPE_FIT_WAVES_PER_SIMD) void fit_kernel(
     shape_batch b, KOpts o, const float* p_init, const float* rec, float* p_out, float* chi2,
@@ -37,12 +53,27 @@ __global__ __launch_bounds__(kWave, SHAPE_FIT_WAVES_PER_SIMD) void fit_kernel(
       }
       continue;
     }
-    lm_start<DT, MODEL, MASK, 1, LAYOUT>(b, o, st, p_init, rec, s, W, nullptr, tid);
-    while (!W.L.done && W.L.it < o.max_iter_lm)
-      lm_iterate<DT, MODEL, MASK, 1, LAYOUT, PROF>(b, o, st, W, nullptr, tid);
-    lm_finish<MODEL, MASK>(o, st, W.L, W.sums[W.cur], s, p_out, chi2, perr, iters, status, sweeps,
-                           tid);
-    __syncthreads();  // W is reused by the next stamp of this wave
+    if constexpr (SHAPE_FIT_STAGE_F16 && DT == SHAPE_F16_SCALED && LAYOUT == kLayoutRows) {
+      // FP16 stamps of a uniform batch (at most 64 x 64, 8 KiB) are staged in
+      // LDS once and every LM sweep reads them there: at four waves per SIMD
+      // the 16 stamps of a CU (128 KiB) fit beside the LM state, while the
+      // waves' stamps together exceed the L2.
+      __shared__ __align__(16) _Float16 lds_px[kWave * kWave];
+      const uint4* src = reinterpret_cast<const uint4*>(static_cast<const _Float16*>(b.pixels) +
+                                                        st.off);
+      for (int q = tid; q < st.npix / 8; q += kWave) reinterpret_cast<uint4*>(lds_px)[q] = src[q];
+      wave_sync();
+      shape_batch bl = b;
+      bl.pixels = lds_px;
+      Stamp sl = st;
+      sl.off = 0;
+      fit_one<DT, MODEL, MASK, LAYOUT, PROF>(bl, o, sl, p_init, rec, s, W, p_out, chi2, perr,
+                                             iters, status, sweeps, tid);
+    } else {
+      fit_one<DT, MODEL, MASK, LAYOUT, PROF>(b, o, st, p_init, rec, s, W, p_out, chi2, perr,
+                                             iters, status, sweeps, tid);
+    }
+    __syncthreads();  // W (and the staged stamp) are reused by the next stamp of this wave
   }
 }
 

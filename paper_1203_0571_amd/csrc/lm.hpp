@@ -64,42 +64,42 @@ __device__ __forceinline__ void store_L(LmShared& W, const LmState& L, int tid) 
 }
 __device__ __forceinline__ LmState load_L(const LmShared& W) { return W.L; }
 
-// Cholesky solve of the N x N SPD system M x = rhs (lower triangle of M used,
-// overwritten by the factor); one reciprocal per pivot, no other divisions.
-// Returns false if M is not positive definite.
-template <int N>
-__device__ __forceinline__ bool chol_solve(double (&M)[N][N], double (&x)[N]) {
-  double inv[N];
+// A double as lane l holds it (the same value in every lane).
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Gauss-Jordan elimination across the lanes of one wave for an SPD system:
+// lane r < N holds row r of [A | B] in a[] and b[] (lanes >= N hold zeros).
+// No pivoting is needed (A is SPD: every pivot is positive); each step
+// broadcasts the pivot row with readlane, so the whole matrix never sits in
+// one lane's registers.  Afterwards lane r holds row r of A^-1 B in b[].
+// Returns false (on every lane) if a pivot is not positive.  Every lane of
+// the wave must call it.
+template <int N, int M>
+__device__ __forceinline__ bool gj_solve(double (&a)[N], double (&b)[M], int lane) {
+  bool ok = true;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    double s = M[j][j];
+    const double piv = read_lane(a[j], j);
+    ok = ok && piv > 0.0;
+    const double ip = 1.0 / piv;
+    const double f = (lane == j) ? 0.0 : a[j];
 #pragma unroll
-    for (int l = 0; l < j; ++l) s -= M[j][l] * M[j][l];
-    if (!(s > 0.0)) return false;
-    inv[j] = 1.0 / sqrt(s);
+    for (int c = 0; c < N; ++c) {
+      const double pc = read_lane(a[c], j) * ip;
+      a[c] = (lane == j) ? pc : fma(-f, pc, a[c]);
+    }
 #pragma unroll
-    for (int i = j + 1; i < N; ++i) {
-      double v = M[i][j];
-#pragma unroll
-      for (int l = 0; l < j; ++l) v -= M[i][l] * M[j][l];
-      M[i][j] = v * inv[j];
+    for (int c = 0; c < M; ++c) {
+      const double pc = read_lane(b[c], j) * ip;
+      b[c] = (lane == j) ? pc : fma(-f, pc, b[c]);
     }
   }
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    double v = x[i];
-#pragma unroll
-    for (int l = 0; l < i; ++l) v -= M[i][l] * x[l];
-    x[i] = v * inv[i];
-  }
-#pragma unroll
-  for (int i = N - 1; i >= 0; --i) {
-    double v = x[i];
-#pragma unroll
-    for (int l = i + 1; l < N; ++l) v -= M[l][i] * x[l];
-    x[i] = v * inv[i];
-  }
-  return true;
+  return ok;
 }
 
 // Synchronise a team of TEAM waves (a lone wave needs no barrier).
@@ -311,30 +311,43 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
     W.M[tid] = v;
   }
   team_sync<TEAM>();
-  // Phase 1b: one thread solves the step and forms the trial point.
+  // Phase 1b: the first wave solves the damped system (lane r < NN holds row
+  // r), then one thread forms the trial point.
+  double xr = 0.0;
+  bool solved = false;
+  if (tid < kWave) {
+    double a[NN], rhs[1];
+#pragma unroll
+    for (int c = 0; c < NN; ++c) {
+      const int hi = tid > c ? tid : c, lo = tid > c ? c : tid;
+      a[c] = tid < NN ? W.M[hi * (hi + 1) / 2 + lo] : 0.0;
+    }
+    rhs[0] = 0.0;
+#pragma unroll
+    for (int r = 0; r < NN; ++r)
+      if (tid == r) rhs[0] = W.sums[cur][sg(nth_bit(NL, r))];
+    solved = gj_solve<NN, 1>(a, rhs, tid);
+    xr = rhs[0];
+  }
+  double x[NN];
+#pragma unroll
+  for (int r = 0; r < NN; ++r) x[r] = read_lane(xr, r);
   if (tid == 0) {
     LmState L = W.L;
     const double* C = W.sums[cur];
-    bool ok = true;
+    bool ok = solved;
     if constexpr (has(LIN, 6) && has(LIN, 7))
-      ok = C[sa(6, 6)] * C[sa(7, 7)] - C[sa(6, 7)] * C[sa(6, 7)] > 0.0;
+      ok = ok && C[sa(6, 6)] * C[sa(7, 7)] - C[sa(6, 7)] * C[sa(6, 7)] > 0.0;
     else if constexpr (has(LIN, 6))
-      ok = C[sa(6, 6)] > 0.0;
+      ok = ok && C[sa(6, 6)] > 0.0;
     else if constexpr (has(LIN, 7))
-      ok = C[sa(7, 7)] > 0.0;
-    double M[NN][NN], x[NN];
-#pragma unroll
-    for (int a = 0; a < NN; ++a) {
-#pragma unroll
-      for (int c = 0; c <= a; ++c) M[a][c] = W.M[a * (a + 1) / 2 + c];
-      x[a] = C[sg(nth_bit(NL, a))];
-    }
+      ok = ok && C[sa(7, 7)] > 0.0;
     ++L.it;
     bool inside = false;
     double smax = 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) W.pt[k] = L.p[k];
-    if (!ok || !chol_solve<NN>(M, x)) {
+    if (!ok) {
       L.stt |= SHAPE_ST_SINGULAR;
     } else {
       double pt[8];

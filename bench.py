@@ -306,10 +306,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if chosen == "plain" else "f16 storage, f32 math",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "sersic64h: 262,144 x 64x64 Sersic stamps, seed 0",
                    "stamps": n, "chosen_form": chosen, "free_params": 8,
+                   "storage": "f32" if chosen == "plain" else "f16 x per-stamp scale",
                    "max_iter_lm": opts.max_iter_lm,
                    "forms": {f: {"objects_per_s": round(r["objs"], 1),
                                  "ms_per_step": round(r["elapsed"] / args.steps * 1e3, 4),

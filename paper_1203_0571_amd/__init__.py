@@ -211,17 +211,22 @@ class DeviceBatch:
 
     @staticmethod
     def from_host(batch, device="cuda", uniform=None):
-        """Upload a synth.Batch (numpy) to the GPU."""
+        """Upload a synth.Batch (numpy) to the GPU.  A batch of one side is
+        passed as side0 (no side or offset arrays: the kernels then take
+        their uniform-side paths), with the model array only if it has a
+        model other than Sersic."""
         dev = torch.device(device)
         sides = batch.sides
         if uniform is None:
-            uniform = batch.n > 0 and bool((sides == sides[0]).all()) and not batch.model.any()
+            uniform = batch.n > 0 and bool((sides == sides[0]).all())
         pix = torch.from_numpy(batch.pixels).to(dev)
         kw = dict(pixels=pix, sigma=torch.from_numpy(batch.sigma).to(dev))
         if batch.scale is not None:
             kw["scale"] = torch.from_numpy(batch.scale).to(dev)
         if uniform:
             kw["side0"] = int(sides[0]) if batch.n else 4
+            if batch.model.any():
+                kw["model"] = torch.from_numpy(batch.model).to(dev)
         else:
             kw["offsets"] = torch.from_numpy(batch.offsets).to(dev)
             kw["sides"] = torch.from_numpy(sides).to(dev)

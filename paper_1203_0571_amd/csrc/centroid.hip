@@ -3,6 +3,7 @@
 // Sec. 4.1 (starting point): the brightest pixel, and r50 from the growth
 // curve about it; Sec. 2: Gaussian-weighted first moments, the centre moving
 // by (<x>/N)/k with the fixed gain k.
+#include "columns.hpp"
 #include "kernels.hpp"
 
 namespace shape {
@@ -50,9 +51,10 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
       continue;
     }
     const int W = SIDE ? SIDE : st.side;
-    // The stamp: in registers for a side that divides 64, read from memory
-    // on every pass otherwise.
+    // The stamp: in registers for a side that divides 64 (px), read from
+    // memory column by column on every pass otherwise (cols).
     const StampPixels<DT, SIDE> px(b, st, lane);
+    const StampColumns<DT> cols(b, st, lane);
     constexpr int kR = SIDE ? kWave / SIDE : 1;   // rows between a lane's slots
     const int il = SIDE ? lane / SIDE : 0, jl = SIDE ? (lane & (SIDE - 1)) : 0;
 
@@ -85,15 +87,25 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
         if (il == kR - 1) border += (double)px.v[kSlots - 1];
       }
     } else {
-      px.each([&](float v, int k, int i, int j) {
-        nonfinite |= !__builtin_isfinite(v);
-        if (i == 0 || j == 0 || i == W - 1 || j == W - 1) border += (double)v;
-        if (v > best) {  // k increases, so ties keep the lowest index
-          best = v;
-          besti = k;
+      for (int c = 0; c < cols.ncol; ++c) {
+        const int j = cols.col(c);
+        const bool bcol = j == 0 || j == W - 1;
+#pragma unroll 4
+        for (int m = 0; m < cols.rows; ++m) {
+          bool in;
+          const float v = cols.at(c, m, in);
+          if (in) {
+            const int i = cols.row(m), k = i * W + j;
+            nonfinite |= !__builtin_isfinite(v);
+            if (bcol || i == 0 || i == W - 1) border += (double)v;
+            if (v > best || (v == best && k < besti)) {  // ties keep the lowest index
+              best = v;
+              besti = k;
+            }
+            amax = fmaxf(amax, fabsf(v));
+          }
         }
-        amax = fmaxf(amax, fabsf(v));
-      });
+      }
     }
     if (wave_any(nonfinite)) {
       if (lane < SHAPE_REC_LEN) out[lane] = qnan();
@@ -157,9 +169,16 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
         }
       }
     } else {
-      px.each([&](float v, int, int i, int j) {
-        deposit(v, __mul24(i - i0, i - i0) + __mul24(j - j0, j - j0));
-      });
+      for (int c = 0; c < cols.ncol; ++c) {
+        const int j = cols.col(c), dj2 = __mul24(j - j0, j - j0);
+#pragma unroll 4
+        for (int m = 0; m < cols.rows; ++m) {
+          bool in;
+          const float v = cols.at(c, m, in);
+          const int di = cols.row(m) - i0;
+          if (in) deposit(v, __mul24(di, di) + dj2);
+        }
+      }
     }
     __syncthreads();
     // Every lane scans the rings (LDS broadcast reads) and reaches the same r50.
@@ -200,7 +219,7 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
         // once; the column sums run in FP32 over blocks of up to 8 rows and
         // in FP64 across blocks and lanes.
         constexpr int kSlots = StampPixels<DT, SIDE>::kSlots;
-        constexpr int kBlk = kSlots < 8 ? kSlots : 8;
+        constexpr int kBlk = kSlots < kColumnBlock ? kSlots : kColumnBlock;
         float ilf = (float)il, jlf = (float)jl;
         asm volatile("" : "+v"(ilf), "+v"(jlf));
         const float t1 = jlf - xf, tb = ilf - yf;
@@ -223,15 +242,30 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
         Sx = wx * (double)t1 * s0;
         Sy = wx * s1;
       } else {
+        // the same factoring down each column the lane owns in memory
         N = Sx = Sy = 0.0;
-        px.each([&](float v, int, int i, int j) {
-          float t1 = (float)j - xf, t2 = (float)i - yf;
-          float w = fast_exp2(-(t1 * t1 + t2 * t2) * c2);
-          float fw = (v - skyf) * w;
-          N += (double)fw;
-          Sx += (double)(fw * t1);
-          Sy += (double)(fw * t2);
-        });
+        for (int c = 0; c < cols.ncol; ++c) {
+          const float t1 = (float)cols.col(c) - xf;
+          double s0 = 0.0, s1 = 0.0;
+          for (int m0 = 0; m0 < cols.rows; m0 += kColumnBlock) {
+            float b0 = 0.0f, b1 = 0.0f;
+#pragma unroll
+            for (int q = 0; q < kColumnBlock; ++q) {
+              bool in;
+              const float v = cols.at(c, m0 + q, in);
+              const float t2 = (float)cols.row(m0 + q) - yf;
+              const float fe = in ? (v - skyf) * fast_exp2(-(t2 * t2) * c2) : 0.0f;
+              b0 += fe;
+              b1 = fmaf(fe, t2, b1);
+            }
+            s0 += (double)b0;
+            s1 += (double)b1;
+          }
+          const double wx = (double)fast_exp2(-(t1 * t1) * c2);
+          N += wx * s0;
+          Sx += wx * (double)t1 * s0;
+          Sy += wx * s1;
+        }
       }
     };
     int it = 0;

@@ -7,12 +7,12 @@
 // accumulates the eleven weighted moments
 //   M_pq = sum f W theta1^p theta2^q,  (p, q) in {00, 10, 01, 20, 11, 02,
 //                                                 40, 31, 22, 13, 04}
-// and the 2x2 algebra is done from them in FP64.  From memory (any side) the
-// zeroth, first and second moments (which fix the centroid and e_obs, hence
-// the fixed point) are accumulated in FP64 per pixel and the fourth moments
-// (which only enter the step matrix P) in FP32.  From registers (a side that
-// divides 64) a lane owns one column, so the moments come from five column
-// sums of f W theta2^q, each summed in FP32 over at most 8 rows at a time.
+// and the 2x2 algebra is done from them in FP64.  A lane owns whole pixel
+// columns (theta1 fixed), so the eleven moments come from five column sums
+// of f W theta2^q, each summed in FP32 over at most 8 rows at a time and in
+// FP64 beyond that; the stamp is held in registers when its side divides 64
+// and read by columns from memory otherwise.
+#include "columns.hpp"
 #include "kernels.hpp"
 
 namespace shape {
@@ -22,6 +22,34 @@ struct Mom {
   double m00, m10, m01, m20, m11, m02;
   float m40, m31, m22, m13, m04;
 };
+
+// One pixel's terms of the column sums S_q = sum f W theta2^q, q = 0..4.
+__device__ __forceinline__ void add_pixel(float (&b)[5], float fw, float t2) {
+  b[0] += fw;
+  float g = fw * t2;
+  b[1] += g;
+  g *= t2;
+  b[2] += g;
+  g *= t2;
+  b[3] += g;
+  b[4] = fmaf(g, t2, b[4]);
+}
+
+// A column's contribution to the moments: M_pq = theta1^p S_q.
+__device__ __forceinline__ void add_column(Mom& M, double t1, const double (&S)[5]) {
+  const double p2 = t1 * t1;
+  M.m00 += S[0];
+  M.m10 += t1 * S[0];
+  M.m01 += S[1];
+  M.m20 += p2 * S[0];
+  M.m11 += t1 * S[1];
+  M.m02 += S[2];
+  M.m40 += (float)(p2 * p2 * S[0]);
+  M.m31 += (float)(p2 * t1 * S[1]);
+  M.m22 += (float)(p2 * S[2]);
+  M.m13 += (float)(t1 * S[3]);
+  M.m04 += (float)S[4];
+}
 
 // KSB quantities from the moments (weight ellipticity g, W' = c W).
 struct Ksb {
@@ -97,7 +125,9 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
       continue;
     }
     const int W = SIDE ? SIDE : st.side;
+    // the stamp in registers (side dividing 64) or read by columns
     const StampPixels<DT, SIDE> px(b, st, lane);
+    const StampColumns<DT> cols(b, st, lane);
     const double sigw = r_in[SHAPE_REC_SIGW];
     const float skyf = r_in[SHAPE_REC_SKY0];
     const double c = -1.0 / (2.0 * sigw * sigw);           // W' = c W
@@ -113,74 +143,54 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
       const float a12 = (float)(-4.0 * g2);
       const float xf = (float)x, yf = (float)y;
       Mom M = {};
+      // Every moment is theta1^p times a column sum S_q = sum f W theta2^q
+      // (q = 0..4) down a column the lane owns, taken in FP32 over blocks of
+      // up to kColumnBlock rows and in FP64 across blocks.  Along a column the
+      // exponent is a quadratic in theta2: -cw R^2 = theta2 (A theta2 + B) + C.
+      const float A = -cw * a22;
       if constexpr (SIDE > 0) {
-        // A lane holds one column (jl) at rows il + kR m, so theta1 is fixed
-        // per lane and every moment is theta1^p times a column sum
-        //   S_q = sum f W theta2^q,  q = 0..4,
-        // taken in FP32 over blocks of up to 8 rows and in FP64 across blocks.
-        // The exponent is a quadratic in theta2 with per-lane coefficients:
-        //   -cw R^2 = theta2 (A theta2 + B) + C.
+        // registers: lane column jl at rows il + kR m
         constexpr int kR = kWave / SIDE, kSlots = StampPixels<DT, SIDE>::kSlots;
-        constexpr int kBlk = kSlots < 8 ? kSlots : 8;
+        constexpr int kBlk = kSlots < kColumnBlock ? kSlots : kColumnBlock;
         float il = (float)(lane / SIDE), jl = (float)(lane & (SIDE - 1));
         asm volatile("" : "+v"(il), "+v"(jl));
-        const double t1d = (double)jl - x;
         const float t1 = jl - xf, tb = il - yf;
-        const float A = -cw * a22, B = -cw * (a12 * t1), C = -cw * (a11 * (t1 * t1));
-        double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
+        const float B = -cw * (a12 * t1), C = -cw * (a11 * (t1 * t1));
+        double S[5] = {};
 #pragma unroll
         for (int m0 = 0; m0 < kSlots; m0 += kBlk) {
-          float b0 = 0.0f, b1 = 0.0f, b2 = 0.0f, b3 = 0.0f, b4 = 0.0f;
+          float bs[5] = {};
 #pragma unroll
           for (int m = m0; m < m0 + kBlk; ++m) {
             const float t2 = tb + (float)(kR * m);
-            const float fw = (px.v[m] - skyf) * fast_exp2(fmaf(fmaf(A, t2, B), t2, C));
-            b0 += fw;
-            float g = fw * t2;
-            b1 += g;
-            g *= t2;
-            b2 += g;
-            g *= t2;
-            b3 += g;
-            b4 = fmaf(g, t2, b4);
+            add_pixel(bs, (px.v[m] - skyf) * fast_exp2(fmaf(fmaf(A, t2, B), t2, C)), t2);
           }
-          S0 += (double)b0;
-          S1 += (double)b1;
-          S2 += (double)b2;
-          S3 += (double)b3;
-          S4 += (double)b4;
+#pragma unroll
+          for (int q = 0; q < 5; ++q) S[q] += (double)bs[q];
         }
-        const double p2 = t1d * t1d;
-        M.m00 = S0;
-        M.m10 = t1d * S0;
-        M.m01 = S1;
-        M.m20 = p2 * S0;
-        M.m11 = t1d * S1;
-        M.m02 = S2;
-        M.m40 = (float)(p2 * p2 * S0);
-        M.m31 = (float)(p2 * t1d * S1);
-        M.m22 = (float)(p2 * S2);
-        M.m13 = (float)(t1d * S3);
-        M.m04 = (float)S4;
+        add_column(M, (double)jl - x, S);
       } else {
-        px.each([&](float v, int, int i, int j) {
-          float t1 = (float)j - xf, t2 = (float)i - yf;
-          float s11 = t1 * t1, s22 = t2 * t2, s12 = t1 * t2;
-          float r2 = fmaf(a11, s11, fmaf(a22, s22, a12 * s12));
-          float fw = (v - skyf) * fast_exp2(-r2 * cw);
-          M.m00 += (double)fw;
-          M.m10 += (double)(fw * t1);
-          M.m01 += (double)(fw * t2);
-          float f11 = fw * s11, f22 = fw * s22, f12 = fw * s12;
-          M.m20 += (double)f11;
-          M.m02 += (double)f22;
-          M.m11 += (double)f12;
-          M.m40 = fmaf(f11, s11, M.m40);
-          M.m31 = fmaf(f11, s12, M.m31);
-          M.m22 = fmaf(f11, s22, M.m22);
-          M.m13 = fmaf(f12, s22, M.m13);
-          M.m04 = fmaf(f22, s22, M.m04);
-        });
+        // memory: the lane's column(s) of a stamp of any side
+        for (int cc = 0; cc < cols.ncol; ++cc) {
+          const float t1 = (float)cols.col(cc) - xf;
+          const float B = -cw * (a12 * t1), C = -cw * (a11 * (t1 * t1));
+          double S[5] = {};
+          for (int m0 = 0; m0 < cols.rows; m0 += kColumnBlock) {
+            float bs[5] = {};
+#pragma unroll
+            for (int q = 0; q < kColumnBlock; ++q) {
+              bool in;
+              const float v = cols.at(cc, m0 + q, in);
+              const float t2 = (float)cols.row(m0 + q) - yf;
+              const float fw =
+                  in ? (v - skyf) * fast_exp2(fmaf(fmaf(A, t2, B), t2, C)) : 0.0f;
+              add_pixel(bs, fw, t2);
+            }
+#pragma unroll
+            for (int q = 0; q < 5; ++q) S[q] += (double)bs[q];
+          }
+          add_column(M, (double)cols.col(cc) - x, S);
+        }
       }
       M.m00 = wave_sum(M.m00);
       M.m10 = wave_sum(M.m10);

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SHAPE_ABI_VERSION 1
+#define SHAPE_ABI_VERSION 2
 
 typedef enum {
   SHAPE_OK = 0,
@@ -73,11 +73,12 @@ typedef enum { SHAPE_SERSIC = 0, SHAPE_MOFFAT = 1 } shape_model;
 #define SHAPE_ST_BAD_INPUT        0x100u /* side, sigma, model or offset invalid */
 #define SHAPE_ST_LOST             0x200u /* the centre left the stamp */
 
-/* Per-stamp record written by shape_centroid and shape_moments (8 floats). */
+/* Per-stamp record written by shape_centroid and shape_moments (9 floats). */
 enum {
   SHAPE_REC_X0 = 0, SHAPE_REC_Y0 = 1, SHAPE_REC_E1 = 2, SHAPE_REC_E2 = 3,
   SHAPE_REC_SIGW = 4, SHAPE_REC_R50 = 5, SHAPE_REC_SKY0 = 6, SHAPE_REC_FLUX = 7,
-  SHAPE_REC_LEN = 8
+  SHAPE_REC_SIZE = 8,
+  SHAPE_REC_LEN = 9
 };
 
 typedef struct {
@@ -116,6 +117,12 @@ typedef struct {
                                  at the start (shape_fit_sersic with free_mask 0xF0 and
                                  no model array only, else SHAPE_EUNSUPPORTED) */
   int32_t  reserved;
+  double   tol_sigma;         /* LM stop, also: a step taken at damping lambda <= 1e-3
+                                 with d^T (A / sigma^2) d < tol_sigma^2, A the (profiled,
+                                 damped) normal matrix, i.e. every fitted parameter moves
+                                 by less than tol_sigma times its standard error; the fit
+                                 ends at the trial if it is accepted, else where the step
+                                 began (1e-4; 0 turns this rule off) */
 } shape_opts;
 
 /* Fill `opts` with the defaults above.  Returns SHAPE_EINVAL if opts is NULL. */
@@ -136,7 +143,7 @@ int shape_abi_version(void);
  * brightest pixel, steps centre += (sum f W theta) / (k sum f W) with
  * W = exp(-|theta|^2 / 2 sigma_w^2), f = I - sky0, until both steps are below
  * tol_x or max_iter_centroid steps.
- *   rec    [n][8] out: x0, y0, 0, 0, sigma_w, r50, sky0, total flux
+ *   rec    [n][9] out: x0, y0, 0, 0, sigma_w, r50, sky0, total flux, NaN
  *   iters  [n] out, status [n] out (SHAPE_ST_*)
  */
 int shape_centroid(const shape_batch* batch, const shape_opts* opts, float* rec,
@@ -151,9 +158,16 @@ int shape_centroid(const shape_batch* batch, const shape_opts* opts, float* rec,
  * halving the step while |g_w| > gmax, and centre += (sum f W theta)/(k sum f W).
  * Stops when the centre moves less than tol_x and g_w less than tol_g in a
  * step that was not halved.
- *   rec_in  [n][8] in (from shape_centroid), rec_out [n][8] out:
- *           x0, y0, e1, e2, sigma_w, r50, sky0, flux
- *   iters, status [n] out.  rec_in == rec_out is allowed.
+ *   rec_in  [n][9] in (from shape_centroid), rec_out [n][9] out:
+ *           x0, y0, e1, e2, sigma_w, r50, sky0, flux, size
+ *   iters, status [n] out.  rec_in == rec_out is allowed.  A record with a
+ *   non-finite field other than size gives SHAPE_ST_BAD_INPUT.
+ * size (the profile fit's starting Re; not from the paper): with the last
+ * step's weight, q = sum f W R^2 / sum f W is the weighted second moment of a
+ * Gaussian source exp(-R^2 / 2 s^2) when s^2 = q sigma_w^2 / (2 sigma_w^2 - q);
+ * size = s sqrt(2 ln 2) / sqrt(1 - |g_w|^2), that source's half-light radius
+ * along the model's elliptical radius; NaN unless sum f W > 0 and
+ * 0 < q < 1.96 sigma_w^2.
  */
 int shape_moments(const shape_batch* batch, const shape_opts* opts, const float* rec_in,
                   float* rec_out, int32_t* iters, uint32_t* status, void* stream);
@@ -166,8 +180,9 @@ int shape_moments(const shape_batch* batch, const shape_opts* opts, const float*
  * complement of the amplitude block of J^T J, in FP64 on the device.  Moffat
  * stamps (model = 1) are fitted with beta fixed at opts->moffat_beta.
  *   p_init [n][8] in, or NULL: start from rec (x0, y0, e1, e2 of the moments,
- *          Re = r50 (Moffat rd = r50 / sqrt(2^(1/beta) - 1)), n = n0)
- *   rec    [n][8] in (from shape_moments), used when p_init is NULL
+ *          Re = the record's size, or r50 where it is NaN (Moffat
+ *          rd = r50 / sqrt(2^(1/beta) - 1)), n = n0)
+ *   rec    [n][9] in (from shape_moments), used when p_init is NULL
  *   p_out  [n][8] out; chi2 [n] out; perr [n][8] out or NULL (sqrt of the
  *          diagonal of (J^T J / sigma^2)^-1 over the fitted parameters)
  *   iters, status [n] out; iters counts LM trials (every trial counts).
@@ -252,7 +267,7 @@ typedef struct {
 int shape_queue_default_cfg(shape_queue_cfg* cfg);
 /* Workspace bytes for n stamps (about 450 B per stamp). */
 int shape_queue_workspace_bytes(int64_t n, size_t* bytes);
-/* Starting points (p_init [n][8] or, if NULL, the moments records rec [n][8]). */
+/* Starting points (p_init [n][8] or, if NULL, the moments records rec [n][9]). */
 int shape_queue_start(const shape_batch* batch, const shape_opts* opts, const shape_queue_cfg* cfg,
                       const float* p_init, const float* rec, void* ws, size_t ws_bytes,
                       void* stream);

@@ -69,6 +69,8 @@ def lib():
         L.orc_centroid.argtypes = [d, C.c_int, C.c_double, C.c_double, C.POINTER(Opts), d, d,
                                    C.POINTER(C.c_int), C.POINTER(C.c_uint32)]
         L.orc_ksb_terms.argtypes = [d, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, d, d]
+        L.orc_size.argtypes = [d, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, d]
+        L.orc_size.restype = C.c_double
         L.orc_moments.argtypes = [d, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                   C.c_double, C.POINTER(Opts), d, C.POINTER(C.c_int),
                                   C.POINTER(C.c_uint32)]
@@ -166,11 +168,19 @@ def ksb_terms(img, sky0, sigw, xc, yc, gw):
 def moments(img, sky0, sigw, r50, x, y, o=None):
     img = _f64(img)
     o = o or opts()
-    out = np.zeros(6)
+    out = np.zeros(7)
     it, st = C.c_int(), C.c_uint32(0)
     lib().orc_moments(_dp(img), img.shape[0], sky0, sigw, r50, x, y, C.byref(o), _dp(out),
                       C.byref(it), C.byref(st))
     return out, it.value, st.value
+
+
+def size(img, sky0, sigw, x, y, g):
+    """orc_size: the fit's starting Re from the weighted second moment."""
+    img = _f64(img)
+    gg = _f64(np.asarray(g, dtype=np.float64))
+    return lib().orc_size(_dp(img), img.shape[0], float(sky0), float(sigw), float(x), float(y),
+                          _dp(gg))
 
 
 def linear(img, p, kind=SERSIC):
@@ -226,7 +236,7 @@ def pipeline(batch, o=None, threads=0, pixels_f64=None):
     sig = np.ascontiguousarray(batch.sigma, np.float32)
     mdl = np.ascontiguousarray(batch.model, np.uint8)
     xy = np.zeros((n, 2))
-    mom = np.zeros((n, 6))
+    mom = np.zeros((n, 7))
     p = np.zeros((n, 8))
     c2 = np.zeros(n)
     iters = np.zeros((n, 3), np.int32)

@@ -356,6 +356,38 @@ void orc_ksb_terms(const double* img, int side, double sky0, double sigw,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Starting size for the profile fit (reading, not in the paper): the        */
+/* half-light radius, along the model's elliptical radius, of the Gaussian   */
+/* source that gives the weighted second moment measured with the moments   */
+/* stage's weight.  With W = exp(-R^2 / 2 sigw^2), R^2 = |S(g_w) theta|^2,   */
+/* a source exp(-R^2 / 2 s^2) has <R^2>_fW = 2 s^2 sigw^2 / (s^2 + sigw^2),  */
+/* so s^2 = q sigw^2 / (2 sigw^2 - q) with q = sum f W R^2 / sum f W; the   */
+/* model's radius is R / sqrt(1 - |g|^2) and a Gaussian's half-light radius */
+/* is s sqrt(2 ln 2).  NaN unless sum f W > 0 and 0 < q < 1.96 sigw^2.       */
+/* ------------------------------------------------------------------------ */
+double orc_size(const double* img, int side, double sky0, double sigw, double xc, double yc,
+                const double* gw) {
+  double g1 = gw[0], g2 = gw[1];
+  double inv2s2 = 1.0 / (2.0 * sigw * sigw);
+  double N = 0.0, M = 0.0;
+  for (int i = 0; i < side; ++i) {
+    for (int j = 0; j < side; ++j) {
+      double t1 = j - xc, t2 = i - yc;
+      double u1 = (1.0 - g1) * t1 - g2 * t2, u2 = -g2 * t1 + (1.0 + g1) * t2;
+      double R2 = u1 * u1 + u2 * u2;
+      double fW = (img[i * side + j] - sky0) * exp(-R2 * inv2s2);
+      N += fW;
+      M += fW * R2;
+    }
+  }
+  if (!(N > 0.0)) return NAN;
+  double q = M / N, s2w = sigw * sigw;
+  if (!(q > 0.0 && q < 1.96 * s2w)) return NAN;
+  double s2 = q * s2w / (2.0 * s2w - q);
+  return sqrt(2.0 * log(2.0) * s2 / (1.0 - (g1 * g1 + g2 * g2)));
+}
+
+/* ------------------------------------------------------------------------ */
 /* Joint centroid + ellipticity iteration (Sec. 2 last paragraph; Sec. 3;    */
 /* Sec. 4.1 starting point).  From g_w = 0 (the first step is the original   */
 /* KSB estimate) each step evaluates the App. A/B sums at the current centre */
@@ -376,8 +408,13 @@ void orc_moments(const double* img, int side, double sky0, double sigw, double r
   double xc = x_in, yc = y_in, g[2] = {0.0, 0.0};
   double t[20];
   int it = 0;
+  double last[4] = {NAN, NAN, NAN, NAN};  /* centre and g_w of the last evaluated step */
   while (it < o->max_iter_moments) {
     orc_ksb_terms(img, side, sky0, sigw, xc, yc, g, t);
+    last[0] = xc;
+    last[1] = yc;
+    last[2] = g[0];
+    last[3] = g[1];
     ++it;
     double N = t[0], T = t[3];
     if (!(N > 0.0) || !(T > 0.0)) { *status |= ORC_NONPOSITIVE_FLUX; break; }
@@ -425,6 +462,7 @@ void orc_moments(const double* img, int side, double sky0, double sigw, double r
   out[3] = g[1];
   out[4] = sigw;
   out[5] = r50;
+  out[6] = it > 0 ? orc_size(img, side, sky0, sigw, last[0], last[1], last + 2) : NAN;
   *iters = it;
 }
 
@@ -790,7 +828,7 @@ int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
     st[0] = st[1] = st[2] = 0;
     itr[0] = itr[1] = itr[2] = 0;
     for (int k = 0; k < 2; ++k) xy[2 * s + k] = NAN;
-    for (int k = 0; k < 6; ++k) mom[6 * s + k] = NAN;
+    for (int k = 0; k < 7; ++k) mom[7 * s + k] = NAN;
     for (int k = 0; k < 8; ++k) p[8 * s + k] = NAN;
     chi2[s] = NAN;
     if (side < 4 || side > 128 || !(sg > 0.0) || (kind != ORC_SERSIC && kind != ORC_MOFFAT)) {
@@ -814,7 +852,7 @@ int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
     itr[0] = it;
     xy[2 * s] = x;
     xy[2 * s + 1] = y;
-    double* mo = mom + 6 * s;
+    double* mo = mom + 7 * s;
     orc_moments(img, side, sky0, sigw, r50, x, y, o, mo, &it, &st[1]);
     itr[1] = it;
     double pi[8];
@@ -823,7 +861,7 @@ int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
     pi[2] = mo[2];
     pi[3] = mo[3];
     if (kind == ORC_SERSIC) {
-      pi[4] = r50;
+      pi[4] = isfinite(mo[6]) ? mo[6] : r50;
       pi[5] = o->n0;
     } else {
       pi[4] = r50 / sqrt(pow(2.0, 1.0 / o->moffat_beta) - 1.0);
@@ -868,7 +906,7 @@ int orc_star_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
       continue;
     }
     const double* img = pixels + offsets[s];
-    double sky0, r50, flux, sigw, mo[6];
+    double sky0, r50, flux, sigw, mo[7];
     int imax, it;
     uint32_t st = 0;
     orc_init(img, side, &sky0, &imax, &r50, &flux, &sigw, &st);

@@ -79,7 +79,14 @@ void orc_centroid(const double* img, int side, double sky0, double sigw,
 void orc_ksb_terms(const double* img, int side, double sky0, double sigw,
                    double xc, double yc, const double* gw, double* out);
 
-/* Joint centroid + ellipticity iteration (Sec. 2, 3).  out: x0, y0, e1, e2, sigw, r50. */
+/* Starting size for the profile fit from the weighted second moment at the
+ * given centre and weight ellipticity (a reading: see oracle.c); NaN when
+ * undefined. */
+double orc_size(const double* img, int side, double sky0, double sigw, double xc, double yc,
+                const double* gw);
+
+/* Joint centroid + ellipticity iteration (Sec. 2, 3).  out: x0, y0, e1, e2, sigw, r50, and
+ * orc_size at the centre and g_w of the last evaluated step. */
 void orc_moments(const double* img, int side, double sky0, double sigw, double r50,
                  double x_in, double y_in, const orc_opts* o, double* out,
                  int* iters, uint32_t* status);
@@ -109,7 +116,8 @@ void orc_star_moments(const double* img, int side, double sky, double xc, double
 
 /* Whole pipeline over a batch, OpenMP over stamps.  Returns threads used.
  * pixels: FP64 packed stamps; offsets/sides/sigma/model per stamp.
- * Outputs per stamp: xy[2] (centroid), mom[6], p[8], chi2, iters[3], status[3]. */
+ * Outputs per stamp: xy[2] (centroid), mom[7], p[8], chi2, iters[3], status[3]; the fit
+ * of a Sersic stamp starts at Re = mom[6] when it is finite, else r50. */
 int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
                  const int32_t* sides, const float* sigma, const uint8_t* model,
                  const orc_opts* o, double* xy, double* mom, double* p,

@@ -40,7 +40,7 @@ ST_G_CLAMPED = 0x080
 ST_BAD_INPUT = 0x100
 ST_LOST = 0x200
 
-REC_LEN = 8
+REC_LEN = 9
 MASK_ALL = 0xFF
 MASK_SIZE = 0xF0
 
@@ -77,6 +77,7 @@ class ShapeOpts(C.Structure):
         ("moffat_beta", C.c_double),
         ("linear_init", C.c_int32),
         ("reserved", C.c_int32),
+        ("tol_sigma", C.c_double),
     ]
 
 

@@ -25,7 +25,8 @@ int check_opts(const shape_opts* o) {
     return SHAPE_EINVAL;
   if (!(o->k_gain > 0.0) || !(o->tol_x >= 0.0) || !(o->tol_g >= 0.0) || !(o->tol_lm >= 0.0))
     return SHAPE_EINVAL;
-  if (!(o->gmax > 0.0 && o->gmax < 1.0) || !(o->lambda0 > 0.0) || !(o->chi2_rtol >= 0.0))
+  if (!(o->gmax > 0.0 && o->gmax < 1.0) || !(o->lambda0 > 0.0) || !(o->chi2_rtol >= 0.0) ||
+      !(o->tol_sigma >= 0.0))
     return SHAPE_EINVAL;
   if (!(o->n0 >= 0.2 && o->n0 <= 10.0) || !(o->moffat_beta > 1.0)) return SHAPE_EINVAL;
   return SHAPE_OK;
@@ -42,6 +43,7 @@ KOpts kopts(const shape_opts* o) {
   k.tol_g = o->tol_g;
   k.gmax = o->gmax;
   k.tol_lm = o->tol_lm;
+  k.tol_sigma = o->tol_sigma;
   k.lambda0 = o->lambda0;
   k.chi2_rtol = o->chi2_rtol;
   k.n0 = o->n0;
@@ -101,6 +103,7 @@ int shape_default_opts(shape_opts* o) {
   o->moffat_beta = 3.0;
   o->linear_init = 1;
   o->reserved = 0;
+  o->tol_sigma = 1e-4;
   return SHAPE_OK;
 }
 

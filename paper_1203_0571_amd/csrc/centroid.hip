@@ -303,6 +303,7 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
       out[SHAPE_REC_R50] = (float)r50;
       out[SHAPE_REC_SKY0] = (float)sky0;
       out[SHAPE_REC_FLUX] = (float)((double)F / fix);
+      out[SHAPE_REC_SIZE] = qnan();
       iters[s] = it;
       status[s] = stt;
     }

@@ -20,7 +20,7 @@ constexpr double kLn2 = 0.6931471805599453;
 struct KOpts {
   int max_iter_centroid, max_iter_moments, max_iter_lm;
   uint32_t free_mask;
-  double k_gain, tol_x, tol_g, gmax, tol_lm, lambda0, chi2_rtol, n0, moffat_beta;
+  double k_gain, tol_x, tol_g, gmax, tol_lm, lambda0, chi2_rtol, n0, moffat_beta, tol_sigma;
   int linear_init;
 };
 

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
     for (int q = 0; q < SHAPE_REC_LEN; ++q) r_in[q] = in[q];
     bool bad_rec = false;
 #pragma unroll
-    for (int q = 0; q < SHAPE_REC_LEN; ++q) bad_rec |= !__builtin_isfinite(r_in[q]);
+    for (int q = 0; q < SHAPE_REC_SIZE; ++q) bad_rec |= !__builtin_isfinite(r_in[q]);  // size may be NaN
     if (st.bad || bad_rec) {
       __syncthreads();
       if (lane < SHAPE_REC_LEN) out[lane] = qnan();
@@ -134,6 +134,7 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
     const float cw = (float)(kLog2e / (2.0 * sigw * sigw));
     double x = r_in[SHAPE_REC_X0], y = r_in[SHAPE_REC_Y0];
     double g1 = 0.0, g2 = 0.0;
+    double size = qnan();
     uint32_t stt = 0;
     int it = 0;
     while (it < o.max_iter_moments) {
@@ -204,6 +205,17 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
       M.m13 = wave_sum(M.m13);
       M.m04 = wave_sum(M.m04);
       ++it;
+      // the fit's starting size from this step's weighted second moment
+      // q = sum f W R^2 / sum f W (R^2 of the current weight)
+      {
+        const double b11 = (1.0 - g1) * (1.0 - g1) + g2 * g2;
+        const double b22 = (1.0 + g1) * (1.0 + g1) + g2 * g2;
+        const double q = (b11 * M.m20 + b22 * M.m02 - 4.0 * g2 * M.m11) / M.m00;
+        const double s2w = sigw * sigw;
+        size = qnan();
+        if (M.m00 > 0.0 && q > 0.0 && q < 1.96 * s2w)
+          size = sqrt(2.0 * kLn2 * (q * s2w / (2.0 * s2w - q)) / (1.0 - (g1 * g1 + g2 * g2)));
+      }
       if (!(M.m00 > 0.0) || !(M.m20 + M.m02 > 0.0)) {
         stt |= SHAPE_ST_NONPOSITIVE_FLUX;
         break;
@@ -258,6 +270,7 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
       out[SHAPE_REC_R50] = r_in[SHAPE_REC_R50];
       out[SHAPE_REC_SKY0] = r_in[SHAPE_REC_SKY0];
       out[SHAPE_REC_FLUX] = r_in[SHAPE_REC_FLUX];
+      out[SHAPE_REC_SIZE] = (float)size;
       iters[s] = it;
       status[s] = stt;
     }

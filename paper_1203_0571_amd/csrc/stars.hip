@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
 #pragma unroll
     for (int q = 0; q < SHAPE_REC_LEN; ++q) {
       r[q] = rec[s * SHAPE_REC_LEN + q];
-      finite = finite && __builtin_isfinite(r[q]);
+      finite = finite && (q == SHAPE_REC_SIZE || __builtin_isfinite(r[q]));  // size may be NaN
     }
     if (st.bad || !finite) {
       if (lane < 4) out[s * 4 + lane] = qnan();

@@ -53,6 +53,11 @@ def compare(gpu, ref, free_mask=0xFF, label=""):
     out["moments_both"] = int(both1.sum())
     out["moments_dxy"] = float(np.abs(mg[both1, :2] - mo[both1, :2]).max()) if both1.any() else 0.0
     out["moments_de"] = float(np.abs(mg[both1, 2:4] - mo[both1, 2:4]).max()) if both1.any() else 0.0
+    # the fit's starting size (record slot 8 on the GPU, slot 6 of the oracle's)
+    fg, fo = np.isfinite(mg[both1, 8]), np.isfinite(mo[both1, 6])
+    out["size_defined_agree"] = float((fg == fo).mean()) if both1.any() else 1.0
+    fin = fg & fo
+    out["size_rel"] = float(np.abs(mg[both1, 8][fin] / mo[both1, 6][fin] - 1).max()) if fin.any() else 0.0
     out["status1_agree"] = float((st_g[:, 1] == st_o[:, 1]).mean())
     # fit
     both2 = conv(st_g, 2) & conv(st_o, 2)

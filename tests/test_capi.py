@@ -35,19 +35,20 @@ def test_library_exports_every_declared_symbol(shape):
     lib = C.CDLL(shape.LIB_PATH)
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert shape.lib.shape_abi_version() == 1
+    assert shape.lib.shape_abi_version() == 2
 
 
 def test_struct_layout_matches_header(shape):
     # offsets fixed by the header's field order on x86-64 / LP64
     assert C.sizeof(shape.ShapeBatch) == 6 * 8 + 8 + 8 + 4 + 4
-    assert C.sizeof(shape.ShapeOpts) == 4 * 4 + 9 * 8 + 2 * 4
+    assert C.sizeof(shape.ShapeOpts) == 4 * 4 + 9 * 8 + 2 * 4 + 8
 
 
 def test_defaults(shape):
     o = shape.default_opts()
     assert o.max_iter_centroid == 20 and o.max_iter_moments == 20 and o.max_iter_lm == 30
     assert o.k_gain == 0.75 and o.free_mask == 0xFF and o.gmax == 0.95
+    assert o.tol_lm == 1e-5 and o.tol_sigma == 1e-4
     assert shape.lib.shape_default_opts(None) == shape.EINVAL
 
 
@@ -95,7 +96,7 @@ def test_argument_errors_return_einval_without_launch(shape):
     assert L.shape_fit_sersic(C.byref(b), C.byref(o), None, None, out, out, None, out, out,
                               None, None) == shape.EINVAL
     for field, val in [("k_gain", 0.0), ("gmax", 1.0), ("lambda0", -1.0), ("n0", 0.1),
-                       ("max_iter_lm", -1), ("moffat_beta", 1.0)]:
+                       ("max_iter_lm", -1), ("moffat_beta", 1.0), ("tol_sigma", -1.0)]:
         ob = shape.default_opts(**{field: val})
         assert L.shape_centroid(C.byref(b), C.byref(ob), out, out, out, None) == shape.EINVAL
 

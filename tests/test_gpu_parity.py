@@ -25,6 +25,7 @@ def _check_bars(r, min_both_frac, min_ok=1.0):
     assert r["fit_both"] >= min_both_frac * r["n"], r
     assert r["centroid_dxy"] <= BAR_X, r
     assert r["moments_dxy"] <= BAR_X and r["moments_de"] <= BAR_E, r
+    assert r["size_rel"] <= 1e-3 and r["size_defined_agree"] >= 0.99, r
     assert r["fit_x_ok"] >= min_ok and r["fit_e_ok"] >= min_ok and r["fit_rel_ok"] >= min_ok, r
 
 

@@ -300,3 +300,53 @@ def test_status_flags_for_bad_stamps():
                     np.zeros(2, np.uint8), np.zeros((2, 8)), None)
     r = oracle.pipeline(b, oracle.opts(), pixels_f64=b.pixels)
     assert (r["status"] == oracle.BAD_INPUT).all()
+
+
+# --- the fit's starting size (a reading: the paper gives no start for Re) ---
+
+@pytest.mark.parametrize("g,width", [((0.0, 0.0), 2.5), ((0.3, -0.2), 3.0), ((-0.1, 0.45), 4.0)])
+def test_size_closed_form_for_gaussian_sources(g, width):
+    """For a Gaussian source with isophotes |S(g) u| = const the weighted
+    second moment inverts exactly, whatever the weight width: the Gaussian
+    integral of exp(-R^2 / 2 s^2) exp(-R^2 / 2 w^2) R^2 gives
+    <R^2> = 2 s^2 w^2 / (s^2 + w^2), and the half-light radius of
+    exp(-R^2 / 2 s^2) along R / sqrt(1 - |g|^2) is s sqrt(2 ln 2) / sqrt(1 - |g|^2)."""
+    side, x0, y0 = 72, 35.3, 36.6
+    img = elliptical_src(side, g, width, x0, y0)
+    want = width * math.sqrt(2 * math.log(2)) / math.sqrt(1 - g[0] ** 2 - g[1] ** 2)
+    for sigw in (2.0, 3.0, 6.0):
+        assert oracle.size(img + 10.0, 10.0, sigw, x0, y0, g) == pytest.approx(want, rel=1e-9)
+
+
+@pytest.mark.parametrize("re,e", [(2.0, (0.0, 0.0)), (3.0, (0.2, -0.1)), (5.5, (-0.35, 0.25))])
+def test_size_is_re_for_half_index_sersic(re, e):
+    """A Sersic profile of index 1/2 is a Gaussian in the model's elliptical
+    radius with half-light radius Re (b(1/2) = ln 2), so the starting size of
+    the oracle's own rendering is Re."""
+    side = 64
+    p = np.array([31.3, 32.6, e[0], e[1], re, 0.5, 50.0, 0.0])
+    img = oracle.model(side, p)
+    assert oracle.size(img, 0.0, 3.0, p[0], p[1], e) == pytest.approx(re, rel=1e-9)
+
+
+def test_size_undefined_cases():
+    side = 48
+    src = elliptical_src(side, (0.1, 0.0), 3.0, 23.5, 24.5)
+    # no positive weighted flux
+    assert math.isnan(oracle.size(-src, 0.0, 3.0, 23.5, 24.5, (0.1, 0.0)))
+    # a flat image: <R^2> under the weight alone is 2 w^2, no finite source size
+    assert math.isnan(oracle.size(np.full((side, side), 5.0), 0.0, 3.0, 23.5, 24.5, (0.0, 0.0)))
+
+
+def test_moments_report_size_at_their_last_step():
+    """orc_moments returns the starting size evaluated at the centre and g_w
+    of its last step, which for a converged iteration is its output."""
+    side = 96
+    true, g = (48.31, 46.77), (0.25, -0.15)
+    img = elliptical_src(side, g, 3.5, *true) + 10.0
+    o = oracle.opts(tol_x=1e-11, tol_g=1e-11, max_iter_moments=60)
+    out, it, st = oracle.moments(img, 10.0, 4.0, 4.7, 47.0, 47.0, o)
+    assert st & oracle.CONVERGED
+    assert out[6] == pytest.approx(oracle.size(img, 10.0, 4.0, out[0], out[1], out[2:4]), rel=1e-9)
+    assert out[6] == pytest.approx(3.5 * math.sqrt(2 * math.log(2)) / math.sqrt(1 - 0.25 ** 2 - 0.15 ** 2),
+                                   rel=1e-8)

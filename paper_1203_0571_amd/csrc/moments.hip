@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
     const float cw = (float)(kLog2e / (2.0 * sigw * sigw));
     double x = r_in[SHAPE_REC_X0], y = r_in[SHAPE_REC_Y0];
     double g1 = 0.0, g2 = 0.0;
-    double size = qnan();
+    double sq_num = 0.0, sq_den = 0.0, sq_gg = 0.0;
     uint32_t stt = 0;
     int it = 0;
     while (it < o.max_iter_moments) {
@@ -205,17 +205,12 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
       M.m13 = wave_sum(M.m13);
       M.m04 = wave_sum(M.m04);
       ++it;
-      // the fit's starting size from this step's weighted second moment
-      // q = sum f W R^2 / sum f W (R^2 of the current weight)
-      {
-        const double b11 = (1.0 - g1) * (1.0 - g1) + g2 * g2;
-        const double b22 = (1.0 + g1) * (1.0 + g1) + g2 * g2;
-        const double q = (b11 * M.m20 + b22 * M.m02 - 4.0 * g2 * M.m11) / M.m00;
-        const double s2w = sigw * sigw;
-        size = qnan();
-        if (M.m00 > 0.0 && q > 0.0 && q < 1.96 * s2w)
-          size = sqrt(2.0 * kLn2 * (q * s2w / (2.0 * s2w - q)) / (1.0 - (g1 * g1 + g2 * g2)));
-      }
+      // sum f W R^2 (R^2 of this step's weight), sum f W and |g_w|^2: the
+      // fit's starting size comes from the last step's (after the loop)
+      sq_num = ((1.0 - g1) * (1.0 - g1) + g2 * g2) * M.m20 +
+               ((1.0 + g1) * (1.0 + g1) + g2 * g2) * M.m02 - 4.0 * g2 * M.m11;
+      sq_den = M.m00;
+      sq_gg = g1 * g1 + g2 * g2;
       if (!(M.m00 > 0.0) || !(M.m20 + M.m02 > 0.0)) {
         stt |= SHAPE_ST_NONPOSITIVE_FLUX;
         break;
@@ -260,6 +255,15 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
     }
     if (!(stt & (SHAPE_ST_CONVERGED | SHAPE_ST_NONPOSITIVE_FLUX | SHAPE_ST_SINGULAR | SHAPE_ST_LOST)))
       stt |= SHAPE_ST_MAX_ITER;
+    // The fit's starting size: a source exp(-R^2 / 2 s^2) gives the weighted
+    // second moment q = 2 s^2 sigma_w^2 / (s^2 + sigma_w^2); its half-light
+    // radius along the model's radius R / sqrt(1 - |g|^2) is s sqrt(2 ln 2).
+    double size = qnan();
+    {
+      const double q = sq_num / sq_den, s2w = sigw * sigw;
+      if (sq_den > 0.0 && q > 0.0 && q < 1.96 * s2w)
+        size = sqrt(2.0 * kLn2 * (q * s2w / (2.0 * s2w - q)) / (1.0 - sq_gg));
+    }
     __syncthreads();  // all lanes have read the input record
     if (lane == 0) {
       out[SHAPE_REC_X0] = (float)x;

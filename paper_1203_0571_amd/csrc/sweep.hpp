@@ -171,16 +171,39 @@ __host__ __device__ inline constexpr bool rows_layout_fits(int side) {
   return side == 8 || side == 16 || side == 32 || side == 64;
 }
 
+// Pixels of a lane whose chi^2 and J^T r terms the FP32 instance sums in FP32
+// before carrying the partial sum on in FP64 (0: every term in FP64).  A
+// partial of 8 terms rounds by about as much as the FP32 terms themselves.
+#ifndef SHAPE_SWEEP_FLUSH
+#define SHAPE_SWEEP_FLUSH 8
+#endif
+
 template <int DT, int MODEL, uint32_t EM, int STRIDE = kWave, typename T = float,
           int LAYOUT = kLayoutAny>
 __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, const Trial<T>& t,
                              Acc<EM, T>& acc, int tid = -1) {
   using A = Arith<T>;
+  constexpr int kFlush = sizeof(T) == 4 ? SHAPE_SWEEP_FLUSH : 0;
   acc.c2 = 0.0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) acc.g[k] = 0.0;
 #pragma unroll
   for (int k = 0; k < 36; ++k) acc.A[k] = (T)0;
+  T c2p = (T)0, gp[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) gp[k] = (T)0;
+  auto flush = [&]() {
+    if constexpr (kFlush > 0) {
+      acc.c2 += (double)c2p;
+      c2p = (T)0;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        if (!has(EM, a)) continue;
+        acc.g[a] += (double)gp[a];
+        gp[a] = (T)0;
+      }
+    }
+  };
   // d = data, (u1, u2) = offset from the centre, (v1, v2) = S(e) u
   auto pixel = [&](const T d, const T u1, const T u2, const T v1, const T v2) {
     const T q = A::fma(v1, v1, v2 * v2);
@@ -227,11 +250,17 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     J[6] = m0;
     J[7] = (T)1;
     const double rd = (double)r;
-    acc.c2 = fma(rd, rd, acc.c2);
+    if constexpr (kFlush > 0)
+      c2p = A::fma(r, r, c2p);
+    else
+      acc.c2 = fma(rd, rd, acc.c2);
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       if (!has(EM, a)) continue;
-      acc.g[a] = (a == 7) ? acc.g[a] + rd : fma((double)J[a], rd, acc.g[a]);
+      if constexpr (kFlush > 0)
+        gp[a] = (a == 7) ? gp[a] + r : A::fma(J[a], r, gp[a]);
+      else
+        acc.g[a] = (a == 7) ? acc.g[a] + rd : fma((double)J[a], rd, acc.g[a]);
 #pragma unroll
       for (int c = a; c < 8; ++c) {
         if (!has(EM, c)) continue;
@@ -261,14 +290,24 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
       pixel(d, u1, u2, A::fma(t.a12, u2, c1), A::fma(t.a22, u2, c2));
       fi += di;
       k += kWave;
+      if constexpr (kFlush > 0)
+        if (m % kFlush == kFlush - 1) flush();   // m is wave-uniform
     }
   } else {
+    int cnt = 0;
     for_pixels<STRIDE>(st.side, [&](int k, int i, int j) {
       const T d = (T)load_px<DT>(b.pixels, st.off, k, st.scale);
       const T u1 = (T)j - t.x0, u2 = (T)i - t.y0;
       pixel(d, u1, u2, A::fma(t.a11, u1, t.a12 * u2), A::fma(t.a12, u1, t.a22 * u2));
+      if constexpr (kFlush > 0) {
+        if (++cnt == kFlush) {
+          flush();
+          cnt = 0;
+        }
+      }
     }, tid);
   }
+  flush();
 }
 
 // Reduce a sweep's per-lane partial sums over the wave and let lane 0 store

@@ -101,14 +101,23 @@ struct Arith<double> {
   static constexpr double kR2Floor = 1e-8;
 };
 
-// Trial parameters as a sweep instance uses them.
+// Trial parameters as a sweep instance uses them.  With v = S(e) u,
+// R^2 = |v|^2 / D and the amplitude folded into the constants:
+//   Sersic: t = 2^(L ha + hc) (L = log2 R^2), m0 = 2^(nb2 t), c = m0 t,
+//           dm/dRe = c k4, dm/dn = c (L k5a + k5b), h = c k7 / R^2;
+//   Moffat: base = 1 + R^2 irdsq, m0 = base^-beta, c = m0 / base,
+//           dm/drd = c R^2 k4, dm/dbeta = m0 log2(base) k5a, h = c k7;
+// where h = (2 / D) dm/dR^2, so that dm/dx0 = h (N u)_1, dm/dy0 = h (N u)_2
+// with N = -S(e)^2, and dm/de_k = h (w_k + e_k R^2) with w_1 = v2 u2 - v1 u1,
+// w_2 = -(v1 u2 + v2 u1).
 template <typename T>
 struct Trial {
   T x0, y0, e1, e2, a11, a12, a22, invD;
   T I0, sky;
-  // Sersic: t = 2^(L ha + hc), m0 = 2^(nb2 t); Moffat: base = 1 + R^2 irdsq
-  T ha, hc, nb2, b, hinvn, invnRe, ndb, invn2, nlnRe;
-  T beta, irdsq, twoirdsq_rd;
+  T n11, n12, n22;
+  T ha, hc, nb2;
+  T beta, irdsq;
+  T k4, k5a, k5b, k7;
 };
 using TrialF = Trial<float>;
 
@@ -136,6 +145,10 @@ __device__ __forceinline__ Trial<T> make_trial(const double* p, int model, doubl
   t.invD = A::uni(A::rcp((T)(1.0 - p[2] * p[2] - p[3] * p[3])));
   t.I0 = A::uni((T)p[6]);
   t.sky = A::uni((T)p[7]);
+  t.n11 = A::uni((T)(-((1.0 - p[2]) * (1.0 - p[2]) + p[3] * p[3])));
+  t.n12 = A::uni((T)(2.0 * p[3]));
+  t.n22 = A::uni((T)(-((1.0 + p[2]) * (1.0 + p[2]) + p[3] * p[3])));
+  const double I0 = p[6], twoinvD = 2.0 / (1.0 - p[2] * p[2] - p[3] * p[3]);
   if (model == SHAPE_SERSIC) {
     const T n = (T)p[5], Re = (T)p[4];
     const T invn = A::rcp(n), l2Re = A::lg2(Re);
@@ -144,18 +157,18 @@ __device__ __forceinline__ Trial<T> make_trial(const double* p, int model, doubl
     t.ha = A::uni((T)0.5 * invn);
     t.hc = A::uni(-l2Re * invn);
     t.nb2 = A::uni((T)(-b * kLog2e));
-    t.b = A::uni((T)b);
-    t.hinvn = A::uni((T)0.5 * invn);
-    t.invnRe = A::uni(invn * A::rcp(Re));
-    t.ndb = A::uni((T)(-db));
-    t.invn2 = A::uni(invn * invn);
-    t.nlnRe = A::uni(-(T)kLn2 * l2Re);
+    const double in = 1.0 / p[5], lnRe = kLn2 * (double)l2Re;
+    t.k4 = A::uni((T)(I0 * b * in / p[4]));
+    t.k5a = A::uni((T)(I0 * b * in * in * 0.5 * kLn2));
+    t.k5b = A::uni((T)(I0 * (-db - b * in * in * lnRe)));
+    t.k7 = A::uni((T)(-I0 * b * 0.5 * in * twoinvD));
   } else {
-    const T rd = (T)p[4];
-    const T ird = A::rcp(rd);
+    const double ird = 1.0 / p[4];
     t.beta = A::uni((T)beta);
-    t.irdsq = A::uni(ird * ird);
-    t.twoirdsq_rd = A::uni((T)2 * ird * ird * ird);
+    t.irdsq = A::uni((T)(ird * ird));
+    t.k4 = A::uni((T)(I0 * beta * 2.0 * ird * ird * ird));
+    t.k5a = A::uni((T)(-I0 * kLn2));
+    t.k7 = A::uni((T)(-I0 * beta * ird * ird * twoinvD));
   }
   return t;
 }
@@ -204,48 +217,42 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
       }
     }
   };
-  // d = data, (u1, u2) = offset from the centre, (v1, v2) = S(e) u
-  auto pixel = [&](const T d, const T u1, const T u2, const T v1, const T v2) {
+  // d = data, (u1, u2) = offset from the centre, (v1, v2) = S(e) u,
+  // (n1, n2) = N u
+  auto pixel = [&](const T d, const T u1, const T u2, const T v1, const T v2, const T n1,
+                   const T n2) {
     const T q = A::fma(v1, v1, v2 * v2);
     T R2 = q * t.invD;
     const bool floored = R2 < A::kR2Floor;
     R2 = floored ? A::kR2Floor : R2;
     T J[8];
-    T m0, dmdR2;
+    T m0, h;
     if constexpr (MODEL == SHAPE_SERSIC) {
       const T L = A::lg2(R2);
       const T tt = A::ex2(A::fma(L, t.ha, t.hc));
       m0 = A::ex2(t.nb2 * tt);
-      const T w = t.I0 * m0;
-      const T ct = w * t.b * tt;
-      dmdR2 = -ct * A::rcp(R2) * t.hinvn;
-      if constexpr (has(EM, 4)) J[4] = ct * t.invnRe;
-      if constexpr (has(EM, 5)) {
-        const T lns = A::fma(L, (T)(0.5 * kLn2), t.nlnRe);
-        J[5] = A::fma(w * tt, t.ndb, ct * lns * t.invn2);
-      }
+      const T c = m0 * tt;
+      h = c * A::rcp(R2) * t.k7;
+      if constexpr (has(EM, 4)) J[4] = c * t.k4;
+      if constexpr (has(EM, 5)) J[5] = c * A::fma(L, t.k5a, t.k5b);
     } else {
       const T base = A::fma(R2, t.irdsq, (T)1);
       const T lb = A::lg2(base);
       m0 = A::ex2(-t.beta * lb);
-      const T w = t.I0 * m0;
-      const T gb = w * t.beta * A::rcp(base);
-      dmdR2 = -gb * t.irdsq;
-      if constexpr (has(EM, 4)) J[4] = gb * R2 * t.twoirdsq_rd;
-      if constexpr (has(EM, 5)) J[5] = -w * lb * (T)kLn2;   // d/dbeta
+      const T c = m0 * A::rcp(base);
+      h = c * t.k7;
+      if constexpr (has(EM, 4)) J[4] = c * R2 * t.k4;
+      if constexpr (has(EM, 5)) J[5] = m0 * lb * t.k5a;   // d/dbeta
     }
-    dmdR2 = floored ? (T)0 : dmdR2;
+    h = floored ? (T)0 : h;
     const T r = d - A::fma(t.I0, m0, t.sky);
     if constexpr (has(EM, 0) || has(EM, 1)) {
-      const T g2 = dmdR2 * ((T)-2 * t.invD);
-      J[0] = g2 * A::fma(t.a11, v1, t.a12 * v2);
-      J[1] = g2 * A::fma(t.a12, v1, t.a22 * v2);
+      J[0] = h * n1;
+      J[1] = h * n2;
     }
     if constexpr (has(EM, 2) || has(EM, 3)) {
-      const T ti = (T)2 * t.invD;
-      const T qq = q * ti * t.invD;
-      J[2] = dmdR2 * A::fma(ti, A::fma(v2, u2, -v1 * u1), t.e1 * qq);
-      J[3] = dmdR2 * A::fma(ti, -A::fma(v1, u2, v2 * u1), t.e2 * qq);
+      J[2] = h * A::fma(t.e1, R2, A::fma(v2, u2, -v1 * u1));
+      J[3] = h * A::fma(t.e2, R2, -A::fma(v1, u2, v2 * u1));
     }
     J[6] = m0;
     J[7] = (T)1;
@@ -277,7 +284,7 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     const int lane = tid < 0 ? (int)(threadIdx.x & (kWave - 1)) : tid;
     const int sd = st.side;                      // 8, 16, 32 or 64
     const T u1 = (T)(lane & (sd - 1)) - t.x0;
-    const T c1 = t.a11 * u1, c2 = t.a12 * u1;
+    const T c1 = t.a11 * u1, c2 = t.a12 * u1, c3 = t.n11 * u1, c4 = t.n12 * u1;
     const T di = (T)(kWave / sd);
     T fi = (T)(lane / sd);
     const int nstep = st.npix / kWave;
@@ -287,7 +294,8 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     for (int m = 0; m < nstep; ++m) {
       const T d = (T)load_rel<DT>(sp, k, st.scale);
       const T u2 = fi - t.y0;
-      pixel(d, u1, u2, A::fma(t.a12, u2, c1), A::fma(t.a22, u2, c2));
+      pixel(d, u1, u2, A::fma(t.a12, u2, c1), A::fma(t.a22, u2, c2), A::fma(t.n12, u2, c3),
+            A::fma(t.n22, u2, c4));
       fi += di;
       k += kWave;
       if constexpr (kFlush > 0)
@@ -298,7 +306,8 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     for_pixels<STRIDE>(st.side, [&](int k, int i, int j) {
       const T d = (T)load_px<DT>(b.pixels, st.off, k, st.scale);
       const T u1 = (T)j - t.x0, u2 = (T)i - t.y0;
-      pixel(d, u1, u2, A::fma(t.a11, u1, t.a12 * u2), A::fma(t.a12, u1, t.a22 * u2));
+      pixel(d, u1, u2, A::fma(t.a11, u1, t.a12 * u2), A::fma(t.a12, u1, t.a22 * u2),
+            A::fma(t.n11, u1, t.n12 * u2), A::fma(t.n12, u1, t.n22 * u2));
       if constexpr (kFlush > 0) {
         if (++cnt == kFlush) {
           flush();

@@ -31,9 +31,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Algorithmic work of one pixel in one LM sweep of the fit (8 free
-# parameters, Sersic): model + residual 31 FLOP, Jacobian 25, J^T r and chi^2
-# 17, J^T J 63 (FMA = 2 FLOP), plus 4 transcendentals counted as 1 each.
-FLOP_PER_PIXEL_SWEEP = 140.0
+# parameters, Sersic), FMA = 2 FLOP, a transcendental 1: offsets and
+# elliptical radius 9, profile 4 + 3 transcendentals, residual 3, Jacobian 24
+# + 1 transcendental (a shared factor dm/dR^2, the N u products, eight
+# columns), J^T J 63, J^T r and chi^2 17.
+FLOP_PER_PIXEL_SWEEP = 124.0
 # Per pixel per iteration of the other stages (FMA = 2, transcendental = 1):
 # centroid sweep: offsets 2, R^2 3, weight 2, f W 2, three sums 5 -> 14;
 # moments sweep: offsets 2, products 3, R^2 5, weight 2, f W 2, eleven
@@ -42,9 +44,10 @@ FLOP_PER_PIXEL_SWEEP = 140.0
 FLOP_PER_PIXEL_CENTROID = 14.0
 FLOP_PER_PIXEL_MOMENTS = 35.0
 FLOP_PER_PIXEL_STAR_MOFFAT = 11.0
-# The 4-parameter sweep (Re, n free, I0 and sky columns): model + residual
-# 31, Jacobian columns for Re and n 8, J^T J 15, J^T r and chi^2 9.
-FLOP_PER_PIXEL_SWEEP_4 = 63.0
+# The 4-parameter sweep (Re, n free, I0 and sky columns): offsets and radius
+# 9, profile 4 + 3 transcendentals, residual 3, Jacobian columns for Re and n
+# 4, J^T J 15, J^T r and chi^2 9.
+FLOP_PER_PIXEL_SWEEP_4 = 47.0
 # MI355X HBM3E: 8 TB/s.
 HBM_PEAK_GBS = 8000.0
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s; one
@@ -659,7 +662,7 @@ def bench_adjoint(args):
     el = time.perf_counter() - t0
     log("adjoint: %s ms per launch; autograd forward+backward %.3f ms"
         % ({k: round(v, 3) for k, v in ms.items()}, el / args.steps * 1e3))
-    # the algorithm's 140 FLOP per pixel (transcendentals counted once, as in
+    # the algorithm's 124 FLOP per pixel (transcendentals counted once, as in
     # the fit) against the FP64 vector peak: the series for log2 / exp2 are
     # what this instance spends beyond them
     achieved = b.n * 64 * 64 * FLOP_PER_PIXEL_SWEEP / (ms["backward"] * 1e-3) / 1e12

@@ -323,6 +323,30 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
 // them (FP64) at dst: [0] = chi^2 sum, [1 + k] = (J^T r)_k, [9 + tri] = J^T J.
 // One quantity at a time, with scheduling barriers, so the reductions do not
 // all hold registers at once.
+//
+// With six or more free parameters the 36 FP32 J^T J sums are reduced by
+// halving instead: v_permlane32_swap pairs entry j of the lower half-wave with
+// entry j + 18 of the upper one (lanes 0-31 then carry entries 0..17, lanes
+// 32-63 entries 18..35), v_permlane16_swap does the same between rows of 16
+// (row k then carries entries 9k..9k+8), and a row scan leaves each total in
+// the row's last lane: 90 instructions where one wave sum per entry takes
+// about 360.
+// (The swapped pair is taken into scalar locals before the reinterpretation:
+// reinterpreting the elements of the returned pair in place compiled to an
+// add of the first element to itself.)
+__device__ __forceinline__ void swap_add32(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  const unsigned x = r[0], y = r[1];
+  a = __builtin_bit_cast(float, x) + __builtin_bit_cast(float, y);
+}
+__device__ __forceinline__ void swap_add16(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  const unsigned x = r[0], y = r[1];
+  a = __builtin_bit_cast(float, x) + __builtin_bit_cast(float, y);
+}
+
 template <uint32_t EM, typename T = float>
 __device__ __forceinline__ void reduce_store(const Acc<EM, T>& acc, double* dst, int lane) {
   {
@@ -330,6 +354,38 @@ __device__ __forceinline__ void reduce_store(const Acc<EM, T>& acc, double* dst,
     if (lane == 0) dst[0] = v;
   }
   __builtin_amdgcn_sched_barrier(0);
+  if constexpr (sizeof(T) == 4 && popcount(EM) >= 6) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      if (has(EM, a)) {
+        const double v = wave_sum(acc.g[a]);
+        if (lane == 0) dst[1 + a] = v;
+      } else if (lane == 0) {
+        dst[1 + a] = 0.0;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    float v[36];
+#pragma unroll
+    for (int i = 0; i < 36; ++i) v[i] = acc.A[i];   // unused entries are 0
+#pragma unroll
+    for (int j = 0; j < 18; ++j) swap_add32(v[j], v[j + 18]);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) swap_add16(v[j], v[j + 9]);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      v[j] = dpp::add<dpp::kShr1, 0xf>(v[j]);
+      v[j] = dpp::add<dpp::kShr2, 0xf>(v[j]);
+      v[j] = dpp::add<dpp::kShr4, 0xf>(v[j]);
+      v[j] = dpp::add<dpp::kShr8, 0xf>(v[j]);
+    }
+    if ((lane & 15) == 15) {
+      const int base = 9 + 9 * (lane >> 4);
+#pragma unroll
+      for (int j = 0; j < 9; ++j) dst[base + j] = (double)v[j];
+    }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
     if (has(EM, a)) {

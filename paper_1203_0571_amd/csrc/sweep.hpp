@@ -319,18 +319,19 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
   flush();
 }
 
-// Reduce a sweep's per-lane partial sums over the wave and let lane 0 store
-// them (FP64) at dst: [0] = chi^2 sum, [1 + k] = (J^T r)_k, [9 + tri] = J^T J.
-// One quantity at a time, with scheduling barriers, so the reductions do not
-// all hold registers at once.
+// Reduce a sweep's per-lane partial sums over the wave and store them (FP64)
+// at dst: [0] = chi^2 sum, [1 + k] = (J^T r)_k, [9 + tri] = J^T J.  One
+// quantity at a time by wave sums, with scheduling barriers, so the
+// reductions do not all hold registers at once, and lane 0 stores.
 //
-// With six or more free parameters the 36 FP32 J^T J sums are reduced by
-// halving instead: v_permlane32_swap pairs entry j of the lower half-wave with
-// entry j + 18 of the upper one (lanes 0-31 then carry entries 0..17, lanes
-// 32-63 entries 18..35), v_permlane16_swap does the same between rows of 16
-// (row k then carries entries 9k..9k+8), and a row scan leaves each total in
-// the row's last lane: 90 instructions where one wave sum per entry takes
-// about 360.
+// With six or more free parameters the sums are reduced by halving instead:
+// v_permlane32_swap pairs entry j of the lower half-wave with entry j + 18 of
+// the upper one (lanes 0-31 then carry entries 0..17 of the 36 J^T J sums,
+// lanes 32-63 entries 18..35), v_permlane16_swap does the same between rows
+// of 16 (row k then carries entries 9k..9k+8), and a row scan leaves each
+// total in the row's last lane, which stores it: about 90 instructions for
+// J^T J where one wave sum per entry takes about 360; the 9 FP64 sums go the
+// same way (padded to 12, row k ends with entries 3k..3k+2).
 // (The swapped pair is taken into scalar locals before the reinterpretation:
 // reinterpreting the elements of the returned pair in place compiled to an
 // add of the first element to itself.)
@@ -347,24 +348,54 @@ __device__ __forceinline__ void swap_add16(float& a, float& b) {
   a = __builtin_bit_cast(float, x) + __builtin_bit_cast(float, y);
 }
 
+__device__ __forceinline__ double pair_to_double(unsigned lo, unsigned hi) {
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// The same halving for FP64 values: both 32-bit halves take the same swap.
+__device__ __forceinline__ void swap_add32(double& a, double& b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  const unsigned x0 = lo[0], y0 = lo[1], x1 = hi[0], y1 = hi[1];
+  a = pair_to_double(x0, x1) + pair_to_double(y0, y1);
+}
+__device__ __forceinline__ void swap_add16(double& a, double& b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  const unsigned x0 = lo[0], y0 = lo[1], x1 = hi[0], y1 = hi[1];
+  a = pair_to_double(x0, x1) + pair_to_double(y0, y1);
+}
+
 template <uint32_t EM, typename T = float>
 __device__ __forceinline__ void reduce_store(const Acc<EM, T>& acc, double* dst, int lane) {
-  {
-    const double v = wave_sum(acc.c2);
-    if (lane == 0) dst[0] = v;
-  }
-  __builtin_amdgcn_sched_barrier(0);
   if constexpr (sizeof(T) == 4 && popcount(EM) >= 6) {
+    // chi^2 and J^T r (FP64), padded to 12: after the two swaps row k holds
+    // entries 3k..3k+2 (dst[0] = chi^2, dst[1 + a] = (J^T r)_a)
+    double u[12];
+    u[0] = acc.c2;
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      if (has(EM, a)) {
-        const double v = wave_sum(acc.g[a]);
-        if (lane == 0) dst[1 + a] = v;
-      } else if (lane == 0) {
-        dst[1 + a] = 0.0;
-      }
-      __builtin_amdgcn_sched_barrier(0);
+    for (int a = 0; a < 8; ++a) u[1 + a] = acc.g[a];   // unused entries are 0
+    u[9] = u[10] = u[11] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) swap_add32(u[j], u[j + 6]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) swap_add16(u[j], u[j + 3]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      u[j] = dpp::add<dpp::kShr1, 0xf>(u[j]);
+      u[j] = dpp::add<dpp::kShr2, 0xf>(u[j]);
+      u[j] = dpp::add<dpp::kShr4, 0xf>(u[j]);
+      u[j] = dpp::add<dpp::kShr8, 0xf>(u[j]);
     }
+    if ((lane & 15) == 15 && lane < 48) {
+      const int base = 3 * (lane >> 4);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dst[base + j] = u[j];
+    }
+    __builtin_amdgcn_sched_barrier(0);
     float v[36];
 #pragma unroll
     for (int i = 0; i < 36; ++i) v[i] = acc.A[i];   // unused entries are 0
@@ -386,6 +417,11 @@ __device__ __forceinline__ void reduce_store(const Acc<EM, T>& acc, double* dst,
     }
     return;
   }
+  {
+    const double v = wave_sum(acc.c2);
+    if (lane == 0) dst[0] = v;
+  }
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
     if (has(EM, a)) {

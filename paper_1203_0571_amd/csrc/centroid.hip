@@ -272,9 +272,13 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
     while (it < o.max_iter_centroid) {
       double N, Sx, Sy;
       sweep(N, Sx, Sy);
-      N = wave_sum(N);
-      Sx = wave_sum(Sx);
-      Sy = wave_sum(Sy);
+      {
+        double u[4] = {N, Sx, Sy, 0.0};
+        wave_sum_n(u);
+        N = u[0];
+        Sx = u[1];
+        Sy = u[2];
+      }
       ++it;
       if (!(N > 0.0)) {
         stt |= SHAPE_ST_NONPOSITIVE_FLUX;

@@ -106,6 +106,81 @@ __device__ inline double wave_sum(double v) {
 }
 __device__ inline bool wave_any(bool p) { return __any(p); }
 
+// Halving steps of a wave reduction: the values a (kept) and b are summed
+// over lane pairs, v_permlane32_swap pairing lane l with l + 32 (afterwards
+// lanes 0-31 carry a's sums, lanes 32-63 b's), v_permlane16_swap pairing the
+// rows of 16 within each half (rows 0 and 2 carry a's, rows 1 and 3 b's).
+// (The swapped pair is taken into scalar locals before the reinterpretation:
+// reinterpreting the elements of the returned pair in place compiled to an
+// add of the first element to itself.)
+__device__ __forceinline__ void swap_add32(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  const unsigned x = r[0], y = r[1];
+  a = __builtin_bit_cast(float, x) + __builtin_bit_cast(float, y);
+}
+__device__ __forceinline__ void swap_add16(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  const unsigned x = r[0], y = r[1];
+  a = __builtin_bit_cast(float, x) + __builtin_bit_cast(float, y);
+}
+
+__device__ __forceinline__ double pair_to_double(unsigned lo, unsigned hi) {
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// The same halving for FP64 values: both 32-bit halves take the same swap.
+__device__ __forceinline__ void swap_add32(double& a, double& b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  const unsigned x0 = lo[0], y0 = lo[1], x1 = hi[0], y1 = hi[1];
+  a = pair_to_double(x0, x1) + pair_to_double(y0, y1);
+}
+__device__ __forceinline__ void swap_add16(double& a, double& b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  const unsigned x0 = lo[0], y0 = lo[1], x1 = hi[0], y1 = hi[1];
+  a = pair_to_double(x0, x1) + pair_to_double(y0, y1);
+}
+
+// Sums of N FP64 values (N a multiple of 4) over the wave, every lane
+// receiving all N: two halving steps (row k then carries entries
+// kN/4 .. kN/4 + N/4 - 1), a scan within each row of 16, and the row totals
+// read back from lanes 15, 31, 47 and 63.
+template <int N>
+__device__ inline void wave_sum_n(double (&u)[N]) {
+  static_assert(N % 4 == 0, "N must be a multiple of 4");
+  constexpr int H = N / 2, Q = N / 4;
+#pragma unroll
+  for (int j = 0; j < H; ++j) swap_add32(u[j], u[j + H]);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) swap_add16(u[j], u[j + Q]);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    u[j] = dpp::add<dpp::kShr1, 0xf>(u[j]);
+    u[j] = dpp::add<dpp::kShr2, 0xf>(u[j]);
+    u[j] = dpp::add<dpp::kShr4, 0xf>(u[j]);
+    u[j] = dpp::add<dpp::kShr8, 0xf>(u[j]);
+  }
+  double t[N];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const uint64_t w = __builtin_bit_cast(uint64_t, u[j]);
+      const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)w, 16 * k + 15);
+      const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(w >> 32), 16 * k + 15);
+      t[Q * k + j] = __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] = t[i];
+}
+
 // Walk the pixels owned by thread `tid` of a team of STRIDE threads working on
 // one stamp: k = tid, tid + STRIDE, ... with (row, col).
 template <int STRIDE = kWave, class F>

@@ -193,17 +193,22 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
           add_column(M, (double)cols.col(cc) - x, S);
         }
       }
-      M.m00 = wave_sum(M.m00);
-      M.m10 = wave_sum(M.m10);
-      M.m01 = wave_sum(M.m01);
-      M.m20 = wave_sum(M.m20);
-      M.m11 = wave_sum(M.m11);
-      M.m02 = wave_sum(M.m02);
-      M.m40 = wave_sum(M.m40);
-      M.m31 = wave_sum(M.m31);
-      M.m22 = wave_sum(M.m22);
-      M.m13 = wave_sum(M.m13);
-      M.m04 = wave_sum(M.m04);
+      {
+        double u[12] = {M.m00, M.m10, M.m01, M.m20, M.m11, M.m02, (double)M.m40,
+                        (double)M.m31, (double)M.m22, (double)M.m13, (double)M.m04, 0.0};
+        wave_sum_n(u);
+        M.m00 = u[0];
+        M.m10 = u[1];
+        M.m01 = u[2];
+        M.m20 = u[3];
+        M.m11 = u[4];
+        M.m02 = u[5];
+        M.m40 = (float)u[6];
+        M.m31 = (float)u[7];
+        M.m22 = (float)u[8];
+        M.m13 = (float)u[9];
+        M.m04 = (float)u[10];
+      }
       ++it;
       // sum f W R^2 (R^2 of this step's weight), sum f W and |g_w|^2: the
       // fit's starting size comes from the last step's (after the loop)

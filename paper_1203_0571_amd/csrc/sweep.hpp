@@ -332,43 +332,6 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
 // total in the row's last lane, which stores it: about 90 instructions for
 // J^T J where one wave sum per entry takes about 360; the 9 FP64 sums go the
 // same way (padded to 12, row k ends with entries 3k..3k+2).
-// (The swapped pair is taken into scalar locals before the reinterpretation:
-// reinterpreting the elements of the returned pair in place compiled to an
-// add of the first element to itself.)
-__device__ __forceinline__ void swap_add32(float& a, float& b) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a),
-                                                  __builtin_bit_cast(unsigned, b), false, false);
-  const unsigned x = r[0], y = r[1];
-  a = __builtin_bit_cast(float, x) + __builtin_bit_cast(float, y);
-}
-__device__ __forceinline__ void swap_add16(float& a, float& b) {
-  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a),
-                                                  __builtin_bit_cast(unsigned, b), false, false);
-  const unsigned x = r[0], y = r[1];
-  a = __builtin_bit_cast(float, x) + __builtin_bit_cast(float, y);
-}
-
-__device__ __forceinline__ double pair_to_double(unsigned lo, unsigned hi) {
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-// The same halving for FP64 values: both 32-bit halves take the same swap.
-__device__ __forceinline__ void swap_add32(double& a, double& b) {
-  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
-  const auto hi =
-      __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
-  const unsigned x0 = lo[0], y0 = lo[1], x1 = hi[0], y1 = hi[1];
-  a = pair_to_double(x0, x1) + pair_to_double(y0, y1);
-}
-__device__ __forceinline__ void swap_add16(double& a, double& b) {
-  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
-  const auto hi =
-      __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
-  const unsigned x0 = lo[0], y0 = lo[1], x1 = hi[0], y1 = hi[1];
-  a = pair_to_double(x0, x1) + pair_to_double(y0, y1);
-}
-
 template <uint32_t EM, typename T = float>
 __device__ __forceinline__ void reduce_store(const Acc<EM, T>& acc, double* dst, int lane) {
   if constexpr (sizeof(T) == 4 && popcount(EM) >= 6) {

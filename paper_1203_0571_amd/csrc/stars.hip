@@ -2,8 +2,8 @@
 //
 // About the centre and ellipticity of the moments stage, with R the model's
 // elliptical radius (R^2 = |S(g) theta|^2 / (1 - |g|^2)) and f = I - sky0, each
-// step sums r0 = sum f W, r2 = sum f W R^2, r4 = sum f W R^4 (FP64) for the
-// current weight width w, then:
+// step sums r0 = sum f W, r2 = sum f W R^2, r4 = sum f W R^4 (FP32 over 8
+// pixels of a lane, then FP64) for the current weight width w, then:
 //   Gaussian (Sec. 4.2.1, W = exp(-R^2 / 2 w^2)): sigma = sqrt(r2 / r0),
 //            I0 = r0 / (pi sigma^2)  (exact when w = sigma);
 //   Moffat   (Sec. 4.2.2, W = (1 + R^2 / w^2)^-3): beta = 1 / (r4 r0 / 2 r2^2 - 1),
@@ -33,9 +33,9 @@ __device__ inline float star_r2(const StarGeom& G, int i, int j) {
   return fmaf(v1, v1, v2 * v2) * G.invD;
 }
 
+// One pixel's terms of r0, r2, r4, added to FP32 partials s[0..2].
 template <int PROFILE>
-__device__ inline void star_accumulate(float f, float R2, float c, double& s0, double& s2,
-                                       double& s4) {
+__device__ __forceinline__ void star_accumulate(float f, float R2, float c, float (&s)[3]) {
   float W;
   if constexpr (PROFILE == 0) {
     W = fast_exp2(-R2 * c);
@@ -45,10 +45,13 @@ __device__ inline void star_accumulate(float f, float R2, float c, double& s0, d
   }
   const float fw = f * W;
   const float fw2 = fw * R2;
-  s0 += (double)fw;
-  s2 += (double)fw2;
-  s4 += (double)(fw2 * R2);
+  s[0] += fw;
+  s[1] += fw2;
+  s[2] = fmaf(fw2, R2, s[2]);
 }
+
+// Pixels a lane sums in FP32 before carrying the partial sums on in FP64.
+constexpr int kStarBlock = 8;
 
 template <int DT, int PROFILE>
 __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float* rec, double tol,
@@ -105,19 +108,35 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
     int it = 0;
     while (it < max_iter) {
       const float c = (float)(PROFILE == 0 ? kLog2e / (2.0 * w * w) : 1.0 / (w * w));
-      double s0 = 0.0, s2 = 0.0, s4 = 0.0;
+      double u[4] = {0.0, 0.0, 0.0, 0.0};   // r0, r2, r4 (and a pad)
+      float sp[3] = {0.0f, 0.0f, 0.0f};
+      auto carry = [&]() {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          u[q] += (double)sp[q];
+          sp[q] = 0.0f;
+        }
+      };
       if (cached) {
 #pragma unroll
-        for (int q = 0; q < kCache; ++q) star_accumulate<PROFILE>(cf[q], cr[q], c, s0, s2, s4);
+        for (int q = 0; q < kCache; ++q) {
+          star_accumulate<PROFILE>(cf[q], cr[q], c, sp);
+          if (q % kStarBlock == kStarBlock - 1) carry();
+        }
       } else {
+        int cnt = 0;
         for_pixels(st.side, [&](int k, int i, int j) {
           const float f = load_px<DT>(b.pixels, st.off, k, st.scale) - G.sky;
-          star_accumulate<PROFILE>(f, star_r2(G, i, j), c, s0, s2, s4);
+          star_accumulate<PROFILE>(f, star_r2(G, i, j), c, sp);
+          if (++cnt == kStarBlock) {
+            carry();
+            cnt = 0;
+          }
         });
       }
-      s0 = wave_sum(s0);
-      s2 = wave_sum(s2);
-      s4 = wave_sum(s4);
+      carry();
+      wave_sum_n(u);
+      const double s0 = u[0], s2 = u[1], s4 = u[2];
       ++it;
       r0 = s0;
       if (!(s0 > 0.0) || !(s2 > 0.0)) {

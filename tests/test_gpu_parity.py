@@ -72,6 +72,22 @@ def test_sersic_workloads_8_params(shape, workload, count):
     _check_bars(r, 0.85, min_ok=0.995)
 
 
+def test_standard_error_stop_only_adds_convergence(shape):
+    """The stop on steps below tol_sigma standard errors is an extra way to
+    converge: every stamp that converges without it converges with it (the
+    trajectories agree until the rule fires), and both meet the bars."""
+    b = synth.make("sersic64", count=512)
+    o = shape.default_opts()
+    o0 = shape.default_opts(tol_sigma=0.0)
+    g, g0 = run_gpu(shape, b, o), run_gpu(shape, b, o0)
+    ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
+    for gg, label in ((g, "tol_sigma default"), (g0, "tol_sigma 0")):
+        _check_bars(compare(gg, ref, 0xFF, label), 0.85, min_ok=0.995)
+    c, c0 = (((x["status"][:, 2] & shape.ST_CONVERGED) != 0) for x in (g, g0))
+    assert np.all(c[c0])
+    assert g["iters"][c0, 2].mean() <= g0["iters"][c0, 2].mean()
+
+
 def test_fp16_storage(shape):
     """FP16 stamps with a per-stamp scale: the oracle reads the same dequantised pixels."""
     b = synth.make("sersic64h", count=1024)

@@ -110,11 +110,20 @@ struct Arith<double> {
 // where h = (2 / D) dm/dR^2, so that dm/dx0 = h (N u)_1, dm/dy0 = h (N u)_2
 // with N = -S(e)^2, and dm/de_k = h (w_k + e_k R^2) with w_1 = v2 u2 - v1 u1,
 // w_2 = -(v1 u2 + v2 u1).
+//
+// Along one column of a stamp (u1 fixed) R^2 and the two e-derivative factors
+// are quadratics in u2:
+//   R^2            = qa u2^2 + qb1 u1 u2 + qc2 u1^2,
+//   e1 R^2 + w_1   = p2a u2^2 + e1 qb1 u1 u2 + (e1 qc2 - a11) u1^2,
+//   e2 R^2 + w_2   = p3a u2^2 + (e2 qb1 - 2) u1 u2 + (e2 qc2 - a12) u1^2,
+// with qa = (a12^2 + a22^2) / D, qb1 = 4 a12 / D, qc2 = (a11^2 + a12^2) / D,
+// p2a = e1 qa + a22, p3a = e2 qa - a12 (S(e) = [[a11, a12], [a12, a22]]).
 template <typename T>
 struct Trial {
   T x0, y0, e1, e2, a11, a12, a22, invD;
   T I0, sky;
   T n11, n12, n22;
+  T qa, qb1, qc2, p2a, p3a;
   T ha, hc, nb2;
   T beta, irdsq;
   T k4, k5a, k5b, k7;
@@ -148,6 +157,16 @@ __device__ __forceinline__ Trial<T> make_trial(const double* p, int model, doubl
   t.n11 = A::uni((T)(-((1.0 - p[2]) * (1.0 - p[2]) + p[3] * p[3])));
   t.n12 = A::uni((T)(2.0 * p[3]));
   t.n22 = A::uni((T)(-((1.0 + p[2]) * (1.0 + p[2]) + p[3] * p[3])));
+  {
+    const double a11 = 1.0 - p[2], a12 = -p[3], a22 = 1.0 + p[2];
+    const double iD = 1.0 / (1.0 - p[2] * p[2] - p[3] * p[3]);
+    const double qa = (a12 * a12 + a22 * a22) * iD;
+    t.qa = A::uni((T)qa);
+    t.qb1 = A::uni((T)(4.0 * a12 * iD));
+    t.qc2 = A::uni((T)((a11 * a11 + a12 * a12) * iD));
+    t.p2a = A::uni((T)(p[2] * qa + a22));
+    t.p3a = A::uni((T)(p[3] * qa - a12));
+  }
   const double I0 = p[6], twoinvD = 2.0 / (1.0 - p[2] * p[2] - p[3] * p[3]);
   if (model == SHAPE_SERSIC) {
     const T n = (T)p[5], Re = (T)p[4];
@@ -217,12 +236,12 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
       }
     }
   };
-  // d = data, (u1, u2) = offset from the centre, (v1, v2) = S(e) u,
-  // (n1, n2) = N u
-  auto pixel = [&](const T d, const T u1, const T u2, const T v1, const T v2, const T n1,
-                   const T n2) {
-    const T q = A::fma(v1, v1, v2 * v2);
-    T R2 = q * t.invD;
+  // Per pixel: d = data, R2 = R^2 (unfloored), (n1, n2) = N u and the
+  // e-derivative factors P2 = e1 R^2 + w_1, P3 = e2 R^2 + w_2.  For the FP32
+  // Sersic instance the constant factors k7 (of the x0, y0, e1, e2 columns)
+  // and k4 (of the Re column) are applied to the sums once, after the sweep.
+  constexpr bool kFold = sizeof(T) == 4 && MODEL == SHAPE_SERSIC;
+  auto pixel = [&](const T d, T R2, const T n1, const T n2, const T P2, const T P3) {
     const bool floored = R2 < A::kR2Floor;
     R2 = floored ? A::kR2Floor : R2;
     T J[8];
@@ -232,8 +251,13 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
       const T tt = A::ex2(A::fma(L, t.ha, t.hc));
       m0 = A::ex2(t.nb2 * tt);
       const T c = m0 * tt;
-      h = c * A::rcp(R2) * t.k7;
-      if constexpr (has(EM, 4)) J[4] = c * t.k4;
+      if constexpr (kFold) {
+        h = c * A::rcp(R2);
+        if constexpr (has(EM, 4)) J[4] = c;
+      } else {
+        h = c * A::rcp(R2) * t.k7;
+        if constexpr (has(EM, 4)) J[4] = c * t.k4;
+      }
       if constexpr (has(EM, 5)) J[5] = c * A::fma(L, t.k5a, t.k5b);
     } else {
       const T base = A::fma(R2, t.irdsq, (T)1);
@@ -251,8 +275,8 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
       J[1] = h * n2;
     }
     if constexpr (has(EM, 2) || has(EM, 3)) {
-      J[2] = h * A::fma(t.e1, R2, A::fma(v2, u2, -v1 * u1));
-      J[3] = h * A::fma(t.e2, R2, -A::fma(v1, u2, v2 * u1));
+      J[2] = h * P2;
+      J[3] = h * P3;
     }
     J[6] = m0;
     J[7] = (T)1;
@@ -283,20 +307,24 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     static_assert(STRIDE == kWave, "the row layout is for a wave alone on its stamp");
     const int lane = tid < 0 ? (int)(threadIdx.x & (kWave - 1)) : tid;
     const int sd = st.side;                      // 8, 16, 32 or 64
+    // the lane's column: u1 fixed, the quadratics' per-column coefficients
     const T u1 = (T)(lane & (sd - 1)) - t.x0;
-    const T c1 = t.a11 * u1, c2 = t.a12 * u1, c3 = t.n11 * u1, c4 = t.n12 * u1;
+    const T uu = u1 * u1;
+    const T qb = t.qb1 * u1, qc = t.qc2 * uu;
+    const T p2b = t.e1 * qb, p2c = A::fma(t.e1, qc, -t.a11 * uu);
+    const T p3b = A::fma(t.e2, qb, (T)-2 * u1), p3c = A::fma(t.e2, qc, -t.a12 * uu);
+    const T c3 = t.n11 * u1, c4 = t.n12 * u1;
     const T di = (T)(kWave / sd);
-    T fi = (T)(lane / sd);
+    T u2 = (T)(lane / sd) - t.y0;
     const int nstep = st.npix / kWave;
     const void* sp = stamp_base<DT>(b, st);
     uint32_t k = (uint32_t)lane;
 #pragma unroll 1
     for (int m = 0; m < nstep; ++m) {
       const T d = (T)load_rel<DT>(sp, k, st.scale);
-      const T u2 = fi - t.y0;
-      pixel(d, u1, u2, A::fma(t.a12, u2, c1), A::fma(t.a22, u2, c2), A::fma(t.n12, u2, c3),
-            A::fma(t.n22, u2, c4));
-      fi += di;
+      pixel(d, A::fma(A::fma(t.qa, u2, qb), u2, qc), A::fma(t.n12, u2, c3), A::fma(t.n22, u2, c4),
+            A::fma(A::fma(t.p2a, u2, p2b), u2, p2c), A::fma(A::fma(t.p3a, u2, p3b), u2, p3c));
+      u2 += di;
       k += kWave;
       if constexpr (kFlush > 0)
         if (m % kFlush == kFlush - 1) flush();   // m is wave-uniform
@@ -306,8 +334,11 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     for_pixels<STRIDE>(st.side, [&](int k, int i, int j) {
       const T d = (T)load_px<DT>(b.pixels, st.off, k, st.scale);
       const T u1 = (T)j - t.x0, u2 = (T)i - t.y0;
-      pixel(d, u1, u2, A::fma(t.a11, u1, t.a12 * u2), A::fma(t.a12, u1, t.a22 * u2),
-            A::fma(t.n11, u1, t.n12 * u2), A::fma(t.n12, u1, t.n22 * u2));
+      // (v1, v2) = S(e) u
+      const T v1 = A::fma(t.a11, u1, t.a12 * u2), v2 = A::fma(t.a12, u1, t.a22 * u2);
+      const T R2 = A::fma(v1, v1, v2 * v2) * t.invD;
+      pixel(d, R2, A::fma(t.n11, u1, t.n12 * u2), A::fma(t.n12, u1, t.n22 * u2),
+            A::fma(t.e1, R2, A::fma(v2, u2, -v1 * u1)), A::fma(t.e2, R2, -A::fma(v1, u2, v2 * u1)));
       if constexpr (kFlush > 0) {
         if (++cnt == kFlush) {
           flush();
@@ -317,6 +348,18 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     }, tid);
   }
   flush();
+  if constexpr (kFold) {
+    // the folded constant factors: column a of J is s_a times what was summed
+    const T sc[8] = {t.k7, t.k7, t.k7, t.k7, t.k4, (T)1, (T)1, (T)1};
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      if (!has(EM, a)) continue;
+      acc.g[a] *= (double)sc[a];
+#pragma unroll
+      for (int c = a; c < 8; ++c)
+        if (has(EM, c)) acc.A[tri(a, c)] *= sc[a] * sc[c];
+    }
+  }
 }
 
 // Reduce a sweep's per-lane partial sums over the wave and store them (FP64)

@@ -105,8 +105,10 @@ typedef struct {
   double   tol_x;             /* centroid stop: max |step| in px (1e-4) */
   double   tol_g;             /* ellipticity stop: max |dg_i| (1e-5) */
   double   gmax;              /* bound on |g_w| and |e| (0.95) */
-  double   tol_lm;            /* LM stop: accepted step max_k |d_k|/s_k (1e-5),
-                                 s = (1, 1, 1, 1, Re, n) */
+  double   tol_lm;            /* LM stop: a step with max_k |d_k|/s_k < tol_lm (1e-5),
+                                 s = (1, 1, 1, 1, Re, n); at damping lambda <= 1e-3 the
+                                 fit ends where the step begins (no sweep for it), at
+                                 larger damping once the step is accepted */
   double   lambda0;           /* initial Marquardt damping (1e-3) */
   double   chi2_rtol;         /* accept a trial if chi2' <= chi2 (1 + rtol) (1e-6) */
   double   n0;                /* starting Sersic index (1) */
@@ -117,12 +119,12 @@ typedef struct {
                                  at the start (shape_fit_sersic with free_mask 0xF0 and
                                  no model array only, else SHAPE_EUNSUPPORTED) */
   int32_t  reserved;
-  double   tol_sigma;         /* LM stop, also: a step taken at damping lambda <= 1e-3
-                                 with d^T (A / sigma^2) d < tol_sigma^2, A the (profiled,
-                                 damped) normal matrix, i.e. every fitted parameter moves
-                                 by less than tol_sigma times its standard error; the fit
-                                 ends at the trial if it is accepted, else where the step
-                                 began (1e-4; 0 turns this rule off) */
+  double   tol_sigma;         /* LM stop, also: a step at damping lambda <= 1e-3 with
+                                 d^T (A / sigma^2) d < tol_sigma^2, A the (profiled,
+                                 damped) normal matrix, i.e. every fitted parameter would
+                                 move by less than tol_sigma times its standard error;
+                                 the fit ends where the step begins, with no sweep for
+                                 it (1e-4; 0 turns this rule off) */
 } shape_opts;
 
 /* Fill `opts` with the defaults above.  Returns SHAPE_EINVAL if opts is NULL. */

@@ -48,7 +48,6 @@ struct LmShared {
   LmState L;
   double pt[8];
   double smax;   // the trial step's max_k |d_k| / s_k (-1: no sweep for it)
-  double qstep;  // d^T A_lambda d = d^T g of the trial step
   double M[21];  // damped Schur complement, lower triangle row by row
   int cur;       // which of sums[] holds the current point
 };
@@ -346,7 +345,7 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
       ok = ok && C[sa(7, 7)] > 0.0;
     ++L.it;
     bool inside = false;
-    double smax = 0.0;
+    double smax = 0.0, q = 0.0;   // q = d^T A_lambda d = d^T g
 #pragma unroll
     for (int k = 0; k < 8; ++k) W.pt[k] = L.p[k];
     if (!ok) {
@@ -357,14 +356,12 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
       for (int k = 0; k < 8; ++k) pt[k] = L.p[k];
       const double iscl[8] = {1.0, 1.0, 1.0, 1.0, 1.0 / L.p[4], 1.0 / L.p[5],
                               1.0 / fabs(L.p[6]), 1.0 / st.sigma};
-      double q = 0.0;
 #pragma unroll
       for (int a = 0; a < NN; ++a) {
         pt[nth_bit(NL, a)] += x[a];
         smax = fmax(smax, fabs(x[a]) * iscl[nth_bit(NL, a)]);
         q += x[a] * C[sg(nth_bit(NL, a))];
       }
-      W.qstep = q;
       const double gmax2 = o.gmax * o.gmax;
       inside = pt[2] * pt[2] + pt[3] * pt[3] < gmax2 && pt[4] >= 0.1 &&
                pt[4] <= (double)st.side && pt[6] > 0.0 && __builtin_isfinite(pt[0]) &&
@@ -374,7 +371,20 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
 #pragma unroll
       for (int k = 0; k < 8; ++k) W.pt[k] = pt[k];
     }
-    if (!inside) {  // rejected before any sweep
+    // At small damping the step is the Gauss-Newton step from the current
+    // point; when it is already below the tolerances (max_k |d_k| / s_k <
+    // tol_lm, or d^T A_lambda d = d^T g below tol_sigma^2 sigma^2: d^T A d /
+    // sigma^2 bounds (d_k / sigma_k)^2 for every k and A_lambda >= A, so every
+    // parameter would move by less than tol_sigma standard errors) the current
+    // point is the result and the trial needs no sweep.
+    const double sig2 = st.sigma * st.sigma;
+    const bool small_step = inside && L.lambda <= 1e-3 &&
+                            (smax < o.tol_lm || q < o.tol_sigma * o.tol_sigma * sig2);
+    if (small_step) {
+      L.stt |= SHAPE_ST_CONVERGED;
+      L.done = 1;
+      W.smax = -1.0;  // no sweep for this trial
+    } else if (!inside) {  // rejected before any sweep
       L.lambda *= 10.0;
       if (L.lambda > 1e10) {
         L.stt |= SHAPE_ST_STALLED;
@@ -407,12 +417,6 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
   }
   const double c2t = T[0];
   const double c2c = W.sums[cur][0];
-  // The step, taken at small damping, is short against the parameters'
-  // standard errors: d^T A d / sigma^2 bounds (d_k / sigma_k)^2 for every k,
-  // and A_lambda >= A makes the test conservative.  The point the step starts
-  // from is then as good as the minimum, whether or not the trial is taken.
-  const double sig2 = st.sigma * st.sigma;
-  const bool small_sigma = L.lambda <= 1e-3 && W.qstep < o.tol_sigma * o.tol_sigma * sig2;
   int next = cur;
   if (!inside) {
     L.stt |= SHAPE_ST_AT_BOUND;
@@ -426,14 +430,10 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
     for (int k = 0; k < 8; ++k) L.p[k] = pt[k];
     next = cur ^ 1;
     L.lambda = fmax(L.lambda * 0.1, 1e-9);
-    if (smax < o.tol_lm || small_sigma) {
+    if (smax < o.tol_lm) {   // a short step taken at larger damping
       L.stt |= SHAPE_ST_CONVERGED;
       L.done = 1;
     }
-  } else if (small_sigma) {
-    // rejected within the evaluation noise of chi^2 at the minimum
-    L.stt |= SHAPE_ST_CONVERGED;
-    L.done = 1;
   } else {
     L.lambda *= 10.0;
     if (L.lambda > 1e10) {

@@ -38,6 +38,7 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
   // Growth curve: ring sums in fixed point, so the atomics are exact and the
   // result does not depend on the order in which lanes add.
   __shared__ unsigned long long ring[kMaxRings];
+  __shared__ float wy_row[kWave];   // the weight's row factor (register stamps)
   const int lane = threadIdx.x;
   for (int64_t s = blockIdx.x; s < b.n; s += gridDim.x) {
     const Stamp st = stamp_info(b, s);
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
     const int W = SIDE ? SIDE : st.side;
     // The stamp: in registers for a side that divides 64 (px), read from
     // memory column by column on every pass otherwise (cols).
-    const StampPixels<DT, SIDE> px(b, st, lane);
+    StampPixels<DT, SIDE> px(b, st, lane);
     const StampColumns<DT> cols(b, st, lane);
     constexpr int kR = SIDE ? kWave / SIDE : 1;   // rows between a lane's slots
     const int il = SIDE ? lane / SIDE : 0, jl = SIDE ? (lane & (SIDE - 1)) : 0;
@@ -209,6 +210,11 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
     double x = j0, y = i0;
     const float c2 = (float)(kLog2e / (2.0 * sigw * sigw));
     const float skyf = (float)sky0;
+    // the register stamp becomes f = I - sky0 once, for every step
+    if constexpr (SIDE > 0) {
+#pragma unroll
+      for (int m = 0; m < StampPixels<DT, SIDE>::kSlots; ++m) px.v[m] -= skyf;
+    }
     // Sums N = sum f W, Sx = sum f W theta1, Sy = sum f W theta2 about (x, y).
     auto sweep = [&](double& N, double& Sx, double& Sy) {
       const float xf = (float)x, yf = (float)y;
@@ -218,11 +224,20 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
         // f wy and f wy theta2 down its column and applies wx (and theta1)
         // once; the column sums run in FP32 over blocks of up to 8 rows and
         // in FP64 across blocks and lanes.
+        // The row factor wy is the same for every column: lane r forms it
+        // for row r and the wave reads it back from LDS.
         constexpr int kSlots = StampPixels<DT, SIDE>::kSlots;
         constexpr int kBlk = kSlots < kColumnBlock ? kSlots : kColumnBlock;
+        wave_sync();  // the previous step's reads of wy_row are done
+        {
+          const float tr = (float)lane - yf;
+          wy_row[lane] = fast_exp2(-(tr * tr) * c2);
+        }
+        wave_sync();
         float ilf = (float)il, jlf = (float)jl;
         asm volatile("" : "+v"(ilf), "+v"(jlf));
         const float t1 = jlf - xf, tb = ilf - yf;
+        const float* wy = wy_row + il;
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
         for (int m0 = 0; m0 < kSlots; m0 += kBlk) {
@@ -230,7 +245,7 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
 #pragma unroll
           for (int m = m0; m < m0 + kBlk; ++m) {
             const float t2 = tb + (float)(kR * m);
-            const float fe = (px.v[m] - skyf) * fast_exp2(-(t2 * t2) * c2);
+            const float fe = px.v[m] * wy[kR * m];
             b0 += fe;
             b1 = fmaf(fe, t2, b1);
           }

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
     }
     const int W = SIDE ? SIDE : st.side;
     // the stamp in registers (side dividing 64) or read by columns
-    const StampPixels<DT, SIDE> px(b, st, lane);
+    StampPixels<DT, SIDE> px(b, st, lane);
     const StampColumns<DT> cols(b, st, lane);
     const double sigw = r_in[SHAPE_REC_SIGW];
     const float skyf = r_in[SHAPE_REC_SKY0];
@@ -134,6 +134,11 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
     const float cw = (float)(kLog2e / (2.0 * sigw * sigw));
     double x = r_in[SHAPE_REC_X0], y = r_in[SHAPE_REC_Y0];
     double g1 = 0.0, g2 = 0.0;
+    // the register stamp becomes f = I - sky0 once, for every step
+    if constexpr (SIDE > 0) {
+#pragma unroll
+      for (int m = 0; m < StampPixels<DT, SIDE>::kSlots; ++m) px.v[m] -= skyf;
+    }
     double sq_num = 0.0, sq_den = 0.0, sq_gg = 0.0;
     uint32_t stt = 0;
     int it = 0;
@@ -164,7 +169,7 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
 #pragma unroll
           for (int m = m0; m < m0 + kBlk; ++m) {
             const float t2 = tb + (float)(kR * m);
-            add_pixel(bs, (px.v[m] - skyf) * fast_exp2(fmaf(fmaf(A, t2, B), t2, C)), t2);
+            add_pixel(bs, px.v[m] * fast_exp2(fmaf(fmaf(A, t2, B), t2, C)), t2);
           }
 #pragma unroll
           for (int q = 0; q < 5; ++q) S[q] += (double)bs[q];

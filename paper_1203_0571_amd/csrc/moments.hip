@@ -158,22 +158,39 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
         // registers: lane column jl at rows il + kR m
         constexpr int kR = kWave / SIDE, kSlots = StampPixels<DT, SIDE>::kSlots;
         constexpr int kBlk = kSlots < kColumnBlock ? kSlots : kColumnBlock;
+        // Down the column theta2 = delta + kR k with k = m - kC, so the lane
+        // sums T_j = sum f W k^j (k^j a constant of the unrolled slot) and
+        // turns them into S_q = sum f W theta2^q once per column.
+        constexpr int kC = kSlots / 2;
         float il = (float)(lane / SIDE), jl = (float)(lane & (SIDE - 1));
         asm volatile("" : "+v"(il), "+v"(jl));
         const float t1 = jl - xf, tb = il - yf;
         const float B = -cw * (a12 * t1), C = -cw * (a11 * (t1 * t1));
-        double S[5] = {};
+        double T[5] = {};
 #pragma unroll
         for (int m0 = 0; m0 < kSlots; m0 += kBlk) {
           float bs[5] = {};
 #pragma unroll
           for (int m = m0; m < m0 + kBlk; ++m) {
             const float t2 = tb + (float)(kR * m);
-            add_pixel(bs, px.v[m] * fast_exp2(fmaf(fmaf(A, t2, B), t2, C)), t2);
+            const float fw = px.v[m] * fast_exp2(fmaf(fmaf(A, t2, B), t2, C));
+            const float k1 = (float)(m - kC), k2 = k1 * k1;   // constants once unrolled
+            bs[0] += fw;
+            bs[1] = fmaf(fw, k1, bs[1]);
+            bs[2] = fmaf(fw, k2, bs[2]);
+            bs[3] = fmaf(fw, k2 * k1, bs[3]);
+            bs[4] = fmaf(fw, k2 * k2, bs[4]);
           }
 #pragma unroll
-          for (int q = 0; q < 5; ++q) S[q] += (double)bs[q];
+          for (int q = 0; q < 5; ++q) T[q] += (double)bs[q];
         }
+        const double dl = (double)il + (double)(kR * kC) - y, r = kR;
+        const double d2 = dl * dl, r2 = r * r;
+        const double S[5] = {
+            T[0], dl * T[0] + r * T[1], d2 * T[0] + 2.0 * dl * r * T[1] + r2 * T[2],
+            d2 * dl * T[0] + 3.0 * d2 * r * T[1] + 3.0 * dl * r2 * T[2] + r2 * r * T[3],
+            d2 * d2 * T[0] + 4.0 * d2 * dl * r * T[1] + 6.0 * d2 * r2 * T[2] +
+                4.0 * dl * r2 * r * T[3] + r2 * r2 * T[4]};
         add_column(M, (double)jl - x, S);
       } else {
         // memory: the lane's column(s) of a stamp of any side

@@ -303,6 +303,38 @@ __device__ inline void sersic_bn(double n, double* b, double* db) {
   *db = 2.0 + dh * dzdx / n;
 }
 
+// b(n) and db/dn in FP32 (in = 1/n) for the FP32 sweep's constants, from
+// the FP32 copy of the series (cut at degree kBnDegreeF; the dropped terms
+// are below 2e-11, far under FP32 rounding).
+__device__ inline void sersic_bn_f32(float n, float in, float* b, float* db) {
+  const float x = __builtin_amdgcn_logf(n) * (float)kLn2;
+  const float t = (x - (float)kBnLogLo) * (float)(kBnIntervals / (kBnLogHi - kBnLogLo));
+  const int k = (int)fminf(fmaxf(t, 0.0f), kBnIntervals - 0.5f);
+  const float z = 2.0f * (t - (float)k) - 1.0f, z2 = 2.0f * z;
+  float b1 = 0.0f, b2 = 0.0f, d1 = 0.0f, d2 = 0.0f;
+#pragma unroll
+  for (int i = kBnDegreeF; i >= 1; --i) {
+    const float nb = fmaf(z2, b1, kBnValueF[k][i]) - b2;
+    b2 = b1;
+    b1 = nb;
+    const float nd = fmaf(z2, d1, kBnDerivF[k][i]) - d2;
+    d2 = d1;
+    d1 = nd;
+  }
+  const float h = fmaf(z, b1, kBnValueF[k][0]) - b2;
+  const float dh = fmaf(z, d1, kBnDerivF[k][0]) - d2;
+  *b = fmaf(2.0f, n, h);
+  *db = fmaf(dh * (float)(2.0 * kBnIntervals / (kBnLogHi - kBnLogLo)), in, 2.0f);
+}
+
+// 1/x for a positive normal double: the hardware estimate and two Newton
+// steps (each squares the relative error).
+__device__ inline double rcp_f64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // Hardware transcendentals (v_exp_f32 = 2^x, v_log_f32 = log2, v_rcp_f32).
 __device__ inline float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ inline float fast_log2(float x) { return __builtin_amdgcn_logf(x); }

@@ -86,7 +86,7 @@ __device__ __forceinline__ bool gj_solve(double (&a)[N], double (&b)[M], int lan
   for (int j = 0; j < N; ++j) {
     const double piv = read_lane(a[j], j);
     ok = ok && piv > 0.0;
-    const double ip = 1.0 / piv;
+    const double ip = rcp_f64(piv);   // (a pivot that is not positive fails the solve)
     const double f = (lane == j) ? 0.0 : a[j];
 #pragma unroll
     for (int c = 0; c < N; ++c) {
@@ -153,7 +153,7 @@ __device__ __forceinline__ AmpStep profile_amplitudes(double* S, double I0, int 
     const double a = S[sa(6, 6)], bq = S[sa(6, 7)], c = S[sa(7, 7)];
     const double det = a * c - bq * bq;
     if (!(det > 0.0)) return AmpStep{false, 0.0, 0.0};
-    const double idet = 1.0 / det;
+    const double idet = rcp_f64(det);
     r.d6 = (c * g6 - bq * g7) * idet;
     r.d7 = (a * g7 - bq * g6) * idet;
   } else if constexpr (has(LIN, 6)) {
@@ -163,7 +163,7 @@ __device__ __forceinline__ AmpStep profile_amplitudes(double* S, double I0, int 
     r.d7 = g7 / S[sa(7, 7)];
   }
   const double d6 = r.d6, d7 = r.d7;
-  const double sc = (I0 + d6) / I0;
+  const double sc = (I0 + d6) * rcp_f64(I0);   // I0 > 0 at every evaluated point
   team_sync<TEAM>();
   if (tid == 0) {  // in place: A_NL and g_N still hold the old values here
     S[0] -= g6 * d6 + g7 * d7;
@@ -299,7 +299,7 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
     double v = C[sa(ka, kc)];
     if constexpr (has(LIN, 6) && has(LIN, 7)) {
       const double L00 = C[sa(6, 6)], L01 = C[sa(6, 7)], L11 = C[sa(7, 7)];
-      const double idet = 1.0 / (L00 * L11 - L01 * L01);
+      const double idet = rcp_f64(L00 * L11 - L01 * L01);   // (not positive: the solve fails)
       const double a6 = C[sa(ka, 6)], a7 = C[sa(ka, 7)];
       const double u = (L11 * a6 - L01 * a7) * idet, w = (L00 * a7 - L01 * a6) * idet;
       v -= u * C[sa(kc, 6)] + w * C[sa(kc, 7)];
@@ -354,8 +354,10 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
       double pt[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) pt[k] = L.p[k];
-      const double iscl[8] = {1.0, 1.0, 1.0, 1.0, 1.0 / L.p[4], 1.0 / L.p[5],
-                              1.0 / fabs(L.p[6]), 1.0 / st.sigma};
+      // (the scales only feed the stopping test: FP32 reciprocals)
+      const double iscl[8] = {1.0, 1.0, 1.0, 1.0, (double)fast_rcp((float)L.p[4]),
+                              (double)fast_rcp((float)L.p[5]), (double)fast_rcp(fabsf((float)L.p[6])),
+                              (double)fast_rcp((float)st.sigma)};
 #pragma unroll
       for (int a = 0; a < NN; ++a) {
         pt[nth_bit(NL, a)] += x[a];

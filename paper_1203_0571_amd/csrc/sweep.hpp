@@ -157,9 +157,13 @@ __device__ __forceinline__ Trial<T> make_trial(const double* p, int model, doubl
   t.n11 = A::uni((T)(-((1.0 - p[2]) * (1.0 - p[2]) + p[3] * p[3])));
   t.n12 = A::uni((T)(2.0 * p[3]));
   t.n22 = A::uni((T)(-((1.0 + p[2]) * (1.0 + p[2]) + p[3] * p[3])));
+  // FP32 instance: reciprocals by Newton from the hardware estimate, b(n) from
+  // the FP32 series (its constants are rounded to FP32 in the end)
+  constexpr bool kF32 = sizeof(T) == 4;
+  const double D = 1.0 - p[2] * p[2] - p[3] * p[3];
+  const double iD = kF32 ? rcp_f64(D) : 1.0 / D;
   {
     const double a11 = 1.0 - p[2], a12 = -p[3], a22 = 1.0 + p[2];
-    const double iD = 1.0 / (1.0 - p[2] * p[2] - p[3] * p[3]);
     const double qa = (a12 * a12 + a22 * a22) * iD;
     t.qa = A::uni((T)qa);
     t.qb1 = A::uni((T)(4.0 * a12 * iD));
@@ -167,22 +171,31 @@ __device__ __forceinline__ Trial<T> make_trial(const double* p, int model, doubl
     t.p2a = A::uni((T)(p[2] * qa + a22));
     t.p3a = A::uni((T)(p[3] * qa - a12));
   }
-  const double I0 = p[6], twoinvD = 2.0 / (1.0 - p[2] * p[2] - p[3] * p[3]);
+  const double I0 = p[6], twoinvD = 2.0 * iD;
   if (model == SHAPE_SERSIC) {
     const T n = (T)p[5], Re = (T)p[4];
     const T invn = A::rcp(n), l2Re = A::lg2(Re);
+    const double in = kF32 ? rcp_f64(p[5]) : 1.0 / p[5];
+    const double iRe = kF32 ? rcp_f64(p[4]) : 1.0 / p[4];
     double b, db;
-    sersic_bn(p[5], &b, &db);
+    if constexpr (kF32) {
+      float bf, dbf;
+      sersic_bn_f32((float)p[5], (float)in, &bf, &dbf);
+      b = bf;
+      db = dbf;
+    } else {
+      sersic_bn(p[5], &b, &db);
+    }
     t.ha = A::uni((T)0.5 * invn);
     t.hc = A::uni(-l2Re * invn);
     t.nb2 = A::uni((T)(-b * kLog2e));
-    const double in = 1.0 / p[5], lnRe = kLn2 * (double)l2Re;
-    t.k4 = A::uni((T)(I0 * b * in / p[4]));
+    const double lnRe = kLn2 * (double)l2Re;
+    t.k4 = A::uni((T)(I0 * b * in * iRe));
     t.k5a = A::uni((T)(I0 * b * in * in * 0.5 * kLn2));
     t.k5b = A::uni((T)(I0 * (-db - b * in * in * lnRe)));
     t.k7 = A::uni((T)(-I0 * b * 0.5 * in * twoinvD));
   } else {
-    const double ird = 1.0 / p[4];
+    const double ird = kF32 ? rcp_f64(p[4]) : 1.0 / p[4];
     t.beta = A::uni((T)beta);
     t.irdsq = A::uni((T)(ird * ird));
     t.k4 = A::uni((T)(I0 * beta * 2.0 * ird * ird * ird));

@@ -267,9 +267,10 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
 #pragma unroll
             for (int q = 0; q < kColumnBlock; ++q) {
               bool in;
-              const float v = cols.at(c, m0 + q, in);
+              const float v = cols.at_clamped(c, m0 + q, in);
               const float t2 = (float)cols.row(m0 + q) - yf;
-              const float fe = in ? (v - skyf) * fast_exp2(-(t2 * t2) * c2) : 0.0f;
+              const float w = fast_exp2(-(t2 * t2) * c2);
+              const float fe = (v - skyf) * (in ? w : 0.0f);
               b0 += fe;
               b1 = fmaf(fe, t2, b1);
             }

@@ -44,6 +44,16 @@ struct StampColumns {
     in = on && i < W && j < W;
     return in ? load_rel<DT>(sp, (uint32_t)(i * W + j), scale) : 0.0f;
   }
+  // The pixel at row(m), col(c) clamped into the stamp (slots outside it read
+  // its last row or column; in = false there, and the caller zeroes their
+  // weight): every slot loads, so a block's loads are issued back to back
+  // instead of one masked branch and wait per load.
+  __device__ __forceinline__ float at_clamped(int c, int m, bool& in) const {
+    const int i = row(m), j = col(c);
+    in = on && i < W && j < W;
+    const int ic = i < W ? i : W - 1, jc = j < W ? j : W - 1;
+    return load_rel<DT>(sp, (uint32_t)(ic * W + jc), scale);
+  }
 };
 
 // Rows summed in FP32 before a column sum is carried on in FP64.

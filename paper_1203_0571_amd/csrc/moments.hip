@@ -203,10 +203,10 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
 #pragma unroll
             for (int q = 0; q < kColumnBlock; ++q) {
               bool in;
-              const float v = cols.at(cc, m0 + q, in);
+              const float v = cols.at_clamped(cc, m0 + q, in);
               const float t2 = (float)cols.row(m0 + q) - yf;
-              const float fw =
-                  in ? (v - skyf) * fast_exp2(fmaf(fmaf(A, t2, B), t2, C)) : 0.0f;
+              const float w = fast_exp2(fmaf(fmaf(A, t2, B), t2, C));
+              const float fw = (v - skyf) * (in ? w : 0.0f);
               add_pixel(bs, fw, t2);
             }
 #pragma unroll

@@ -236,7 +236,10 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
         wave_sync();
         float ilf = (float)il, jlf = (float)jl;
         asm volatile("" : "+v"(ilf), "+v"(jlf));
-        const float t1 = jlf - xf, tb = ilf - yf;
+        // theta2 = delta + kR k with k = m - kC (a constant of the unrolled
+        // slot), so the lane sums f wy k and forms the theta2 sum once.
+        constexpr int kC = kSlots / 2;
+        const float t1 = jlf - xf;
         const float* wy = wy_row + il;
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -244,18 +247,18 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
           float b0 = 0.0f, b1 = 0.0f;
 #pragma unroll
           for (int m = m0; m < m0 + kBlk; ++m) {
-            const float t2 = tb + (float)(kR * m);
             const float fe = px.v[m] * wy[kR * m];
             b0 += fe;
-            b1 = fmaf(fe, t2, b1);
+            b1 = fmaf(fe, (float)(m - kC), b1);
           }
           s0 += (double)b0;
           s1 += (double)b1;
         }
         const double wx = (double)fast_exp2(-(t1 * t1) * c2);
+        const double dl = (double)ilf + (double)(kR * kC) - y;
         N = wx * s0;
         Sx = wx * (double)t1 * s0;
-        Sy = wx * s1;
+        Sy = wx * (dl * s0 + (double)kR * s1);
       } else {
         // the same factoring down each column the lane owns in memory
         N = Sx = Sy = 0.0;

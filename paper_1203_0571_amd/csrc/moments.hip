@@ -166,15 +166,19 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
         asm volatile("" : "+v"(il), "+v"(jl));
         const float t1 = jl - xf, tb = il - yf;
         const float B = -cw * (a12 * t1), C = -cw * (a11 * (t1 * t1));
+        // the exponent as a quadratic in k: A t2^2 + B t2 + C with
+        // t2 = tc + kR k, tc = theta2 at the middle slot
+        const float tc = tb + (float)(kR * kC);
+        const float Ak = A * (float)(kR * kR), Bk = (float)kR * fmaf(2.0f * A, tc, B);
+        const float Ck = fmaf(fmaf(A, tc, B), tc, C);
         double T[5] = {};
 #pragma unroll
         for (int m0 = 0; m0 < kSlots; m0 += kBlk) {
           float bs[5] = {};
 #pragma unroll
           for (int m = m0; m < m0 + kBlk; ++m) {
-            const float t2 = tb + (float)(kR * m);
-            const float fw = px.v[m] * fast_exp2(fmaf(fmaf(A, t2, B), t2, C));
             const float k1 = (float)(m - kC), k2 = k1 * k1;   // constants once unrolled
+            const float fw = px.v[m] * fast_exp2(fmaf(fmaf(Ak, k1, Bk), k1, Ck));
             bs[0] += fw;
             bs[1] = fmaf(fw, k1, bs[1]);
             bs[2] = fmaf(fw, k2, bs[2]);

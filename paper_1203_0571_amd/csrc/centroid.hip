@@ -305,7 +305,8 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
         stt |= SHAPE_ST_NONPOSITIVE_FLUX;
         break;
       }
-      double dx = Sx / (o.k_gain * N), dy = Sy / (o.k_gain * N);
+      const double iN = rcp_f64(o.k_gain * N);   // N > 0 here
+      double dx = Sx * iN, dy = Sy * iN;
       x += dx;
       y += dy;
       if (x < 0.0 || y < 0.0 || x > W - 1 || y > W - 1) {

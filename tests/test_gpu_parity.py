@@ -186,3 +186,35 @@ def test_full_size_sampled(shape):
     conv = (g["status"][:, 2] & shape.ST_CONVERGED) != 0
     print("full-size convergence fraction %.4f" % conv.mean())
     assert conv.mean() > 0.85
+
+
+@pytest.mark.parametrize("workload", ["plain32", "sersic64h"])
+def test_register_and_memory_paths_agree(shape, workload):
+    """A uniform batch takes the register-stamp centroid/moments and the
+    column-per-lane fit sweep; the same stamps with a side array take the
+    memory paths and the generic sweep.  Two codings of the same stages: they
+    agree within the parity bars, and their statuses agree."""
+    import torch
+    b = synth.make(workload, count=512)
+    o = shape.default_opts(free_mask=shape.MASK_SIZE) if workload == "plain32" else shape.default_opts()
+    outs = []
+    for uniform in (True, False):
+        db = shape.DeviceBatch.from_host(b, "cuda:0", uniform=uniform)
+        out = shape.pipeline(db, o)
+        torch.cuda.synchronize()
+        outs.append({k: v.cpu().numpy() for k, v in out.items() if hasattr(v, "cpu")})
+    r, m = outs
+    for stage in ("centroid", "moments"):
+        k = 0 if stage == "centroid" else 1
+        ok = ((r["status"][:, k] & m["status"][:, k] & shape.ST_CONVERGED) != 0)
+        assert (r["status"][:, k] == m["status"][:, k]).mean() > 0.99, stage
+        assert ok.mean() > 0.85, stage   # the workloads' own converged fractions (~0.9 at 64^2)
+        assert np.abs(r[stage][ok, :2] - m[stage][ok, :2]).max() <= BAR_X
+        if stage == "moments":
+            assert np.abs(r[stage][ok, 2:4] - m[stage][ok, 2:4]).max() <= BAR_E
+    both = ((r["status"][:, 2] & m["status"][:, 2] & shape.ST_CONVERGED) != 0)
+    assert both.mean() > 0.85
+    assert np.abs(r["p"][both, :2] - m["p"][both, :2]).max() <= BAR_X
+    assert np.abs(r["p"][both, 2:4] - m["p"][both, 2:4]).max() <= BAR_E
+    rel = np.abs(r["p"][both, 4:6] / m["p"][both, 4:6] - 1).max(axis=1)
+    assert (rel <= BAR_REL).mean() >= 0.995

@@ -68,7 +68,8 @@ typedef enum { SHAPE_SERSIC = 0, SHAPE_MOFFAT = 1 } shape_model;
 #define SHAPE_ST_SINGULAR         0x008u /* a 2x2 or normal-equation solve failed */
 #define SHAPE_ST_NONFINITE_INPUT  0x010u /* NaN/Inf pixel */
 #define SHAPE_ST_NONPOSITIVE_FLUX 0x020u /* total or weighted flux <= 0, or I0 <= 0 */
-#define SHAPE_ST_AT_BOUND         0x040u /* an LM trial left the parameter box */
+#define SHAPE_ST_AT_BOUND         0x040u /* the fit ended on the edge of the parameter
+                                            box (see shape_fit_sersic) */
 #define SHAPE_ST_G_CLAMPED        0x080u /* an ellipticity step was halved */
 #define SHAPE_ST_BAD_INPUT        0x100u /* side, sigma, model or offset invalid */
 #define SHAPE_ST_LOST             0x200u /* the centre left the stamp */
@@ -261,7 +262,8 @@ int shape_star_moments(const shape_batch* batch, int32_t profile, const float* r
 typedef struct {
   int32_t team;           /* waves per stamp for stamps with side >= team_min_side: 1, 2, 4 */
   int32_t team_min_side;  /* threshold side for team processing (team > 1) */
-  int32_t grid;           /* persistent workgroups; 0 = as many as fit on the device */
+  int32_t grid;           /* persistent workgroups; 0 = as many as fit on the device;
+                             1 .. 7 are raised to 8 (one per cursor) */
   int32_t reserved;
 } shape_queue_cfg;
 

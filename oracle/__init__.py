@@ -84,7 +84,7 @@ def lib():
                                        C.POINTER(C.c_int), C.POINTER(C.c_uint32)]
         L.orc_pipeline.restype = C.c_int
         L.orc_pipeline.argtypes = [C.c_int64, d, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                   C.POINTER(Opts), d, d, d, d, C.c_void_p, C.c_void_p, C.c_int]
+                                   C.POINTER(Opts), d, d, d, d, d, C.c_void_p, C.c_void_p, C.c_int]
         L.orc_frame_detect.argtypes = [d, C.c_int, C.c_int, C.c_int, d, d, d,
                                        C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p,
                                        C.POINTER(C.c_uint32)]
@@ -239,12 +239,14 @@ def pipeline(batch, o=None, threads=0, pixels_f64=None):
     mom = np.zeros((n, 7))
     p = np.zeros((n, 8))
     c2 = np.zeros(n)
+    perr = np.zeros((n, 8))
     iters = np.zeros((n, 3), np.int32)
     status = np.zeros((n, 3), np.uint32)
     used = lib().orc_pipeline(n, _dp(pix), offs.ctypes.data, sides.ctypes.data, sig.ctypes.data,
                               mdl.ctypes.data, C.byref(o), _dp(xy), _dp(mom), _dp(p), _dp(c2),
-                              iters.ctypes.data, status.ctypes.data, int(threads))
-    return dict(xy=xy, mom=mom, p=p, chi2=c2, iters=iters, status=status, threads=used)
+                              _dp(perr), iters.ctypes.data, status.ctypes.data, int(threads))
+    return dict(xy=xy, mom=mom, p=p, chi2=c2, perr=perr, iters=iters, status=status,
+                threads=used)
 
 
 def star_pipeline(batch, kind, tol=1e-4, max_iter=20, o=None, threads=0):

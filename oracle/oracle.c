@@ -570,6 +570,16 @@ static double jtj_at(const double* jtj, int a, int b) {
   return jtj[a * 8 - a * (a - 1) / 2 + (b - a)];
 }
 
+/* The end point lies on the edge of the box (fitted parameters only). */
+static int at_box_edge(const double* p, int kind, int side, double gmax, uint32_t mask) {
+  const double m = 1e-3;
+  if ((mask & 0x0Cu) && hypot(p[2], p[3]) >= gmax - m) return 1;
+  if ((mask & 0x10u) && (p[4] <= 0.1 * (1.0 + m) || p[4] >= side * (1.0 - m))) return 1;
+  if (kind == ORC_SERSIC && (mask & 0x20u) && (p[5] <= 0.2 * (1.0 + m) || p[5] >= 10.0 * (1.0 - m)))
+    return 1;
+  return 0;
+}
+
 static int in_bounds(const double* p, int kind, int side, double gmax) {
   if (!(p[2] * p[2] + p[3] * p[3] < gmax * gmax)) return 0;
   if (!(p[4] >= 0.1 && p[4] <= side)) return 0;
@@ -631,7 +641,11 @@ static int schur_nl(const double* jtj, const int* nidx, int nn, const int* lidx,
 /* chi^2 (1 + chi2_rtol) is rejected (lambda x 10), otherwise accepted       */
 /* (lambda / 10, floor 1e-9).  Converged when an accepted step has           */
 /* max_k |delta_k| / s_k < tol_lm, s = (1, 1, 1, 1, Re, n); stalled when      */
-/* lambda exceeds 1e10.                                                      */
+/* lambda exceeds 1e10.  A fit that ends with a fitted parameter within a    */
+/* relative 1e-3 of the box (|e| >= gmax - 1e-3; Re <= 0.1 (1 + 1e-3) or      */
+/* >= side (1 - 1e-3); Sersic n <= 0.2 (1 + 1e-3) or >= 10 (1 - 1e-3)) is     */
+/* flagged AT_BOUND: its minimum lies on the box, not at a stationary point   */
+/* of chi^2.                                                                 */
 /* With linear_init = 0 the free amplitudes are not profiled: they start at  */
 /* their linear optimum at the starting shape and are then searched by the   */
 /* same LM together with the shape parameters (the plain form the           */
@@ -685,7 +699,6 @@ void orc_fit(const double* img, int side, double sigma, int kind, const double* 
       inside = in_bounds(pt, kind, side, o->gmax);
     }
     if (!inside) {
-      *status |= ORC_AT_BOUND;
       lambda *= 10.0;
       if (lambda > 1e10) { *status |= ORC_STALLED; break; }
       continue;
@@ -704,6 +717,7 @@ void orc_fit(const double* img, int side, double sigma, int kind, const double* 
     }
   }
   if (!(*status & (ORC_CONVERGED | ORC_STALLED))) *status |= ORC_MAX_ITER;
+  if (at_box_edge(p, kind, side, o->gmax, mask)) *status |= ORC_AT_BOUND;
   if (perr) {
     int idx[8], nf = 0;
     for (int k = 0; k < 8; ++k)
@@ -812,7 +826,7 @@ void orc_star_moments(const double* img, int side, double sky, double xc, double
 int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
                  const int32_t* sides, const float* sigma, const uint8_t* model,
                  const orc_opts* o, double* xy, double* mom, double* p,
-                 double* chi2, int32_t* iters, uint32_t* status, int threads) {
+                 double* chi2, double* perr, int32_t* iters, uint32_t* status, int threads) {
   int used = 1;
 #ifdef _OPENMP
   if (threads > 0) omp_set_num_threads(threads);
@@ -830,6 +844,8 @@ int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
     for (int k = 0; k < 2; ++k) xy[2 * s + k] = NAN;
     for (int k = 0; k < 7; ++k) mom[7 * s + k] = NAN;
     for (int k = 0; k < 8; ++k) p[8 * s + k] = NAN;
+    if (perr)
+      for (int k = 0; k < 8; ++k) perr[8 * s + k] = NAN;
     chi2[s] = NAN;
     if (side < 4 || side > 128 || !(sg > 0.0) || (kind != ORC_SERSIC && kind != ORC_MOFFAT)) {
       st[0] = st[1] = st[2] = ORC_BAD_INPUT;
@@ -872,7 +888,7 @@ int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
     pi[6] = 1.0;
     pi[7] = sky0;
     double c2;
-    orc_fit(img, side, sg, kind, pi, o, p + 8 * s, &c2, &it, &st[2], NULL);
+    orc_fit(img, side, sg, kind, pi, o, p + 8 * s, &c2, &it, &st[2], perr ? perr + 8 * s : NULL);
     itr[2] = it;
     chi2[s] = c2;
   }

@@ -25,7 +25,7 @@ extern "C" {
 #define ORC_SINGULAR         0x008u
 #define ORC_NONFINITE_INPUT  0x010u
 #define ORC_NONPOSITIVE_FLUX 0x020u
-#define ORC_AT_BOUND         0x040u
+#define ORC_AT_BOUND         0x040u  /* the fit ended on the edge of the parameter box */
 #define ORC_G_CLAMPED        0x080u
 #define ORC_BAD_INPUT        0x100u
 #define ORC_LOST             0x200u
@@ -116,12 +116,14 @@ void orc_star_moments(const double* img, int side, double sky, double xc, double
 
 /* Whole pipeline over a batch, OpenMP over stamps.  Returns threads used.
  * pixels: FP64 packed stamps; offsets/sides/sigma/model per stamp.
- * Outputs per stamp: xy[2] (centroid), mom[7], p[8], chi2, iters[3], status[3]; the fit
- * of a Sersic stamp starts at Re = mom[6] when it is finite, else r50. */
+ * Outputs per stamp: xy[2] (centroid), mom[7], p[8], chi2, perr[8] (may be NULL:
+ * sqrt(diag((J^T J / sigma^2)^-1)) over the fitted parameters at the result),
+ * iters[3], status[3]; the fit of a Sersic stamp starts at Re = mom[6] when it
+ * is finite, else r50. */
 int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
                  const int32_t* sides, const float* sigma, const uint8_t* model,
                  const orc_opts* o, double* xy, double* mom, double* p,
-                 double* chi2, int32_t* iters, uint32_t* status, int threads);
+                 double* chi2, double* perr, int32_t* iters, uint32_t* status, int threads);
 
 /* Front end on a whole H x W frame (Sec. 4.1, starting point): border-mean
  * sky, brightest pixel, growth-curve r50 about it, and the cut-out square

@@ -105,7 +105,7 @@ class ShapeFrames(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libshape.so is not built (run __graft_entry__.build() or "
-                          "python -m paper_1203_0571_amd.build); there is no fallback")
+                          "python __graft_entry__.py); there is no fallback")
     lib = C.CDLL(LIB_PATH)
     vp, bp, op = C.c_void_p, C.POINTER(ShapeBatch), C.POINTER(ShapeOpts)
     lib.shape_abi_version.restype = C.c_int
@@ -196,7 +196,35 @@ class DeviceBatch:
     def device(self):
         return self.pixels.device
 
+    def validate(self):
+        """Raise ValueError unless every tensor is contiguous, on the pixels'
+        device, and of the dtype and length the library reads (a strided or
+        mistyped tensor would make the kernels read past its end)."""
+        n, dev = self.n, self.pixels.device
+        if self.pixels.dtype not in (torch.float32, torch.float16):
+            raise ValueError("pixels must be float32, or float16 with a scale")
+        if (self.pixels.dtype == torch.float16) != (self.scale is not None):
+            raise ValueError("float16 pixels need a per-stamp scale (and only they)")
+        want = [("pixels", self.pixels, self.pixels.dtype, None),
+                ("sigma", self.sigma, torch.float32, (n,)),
+                ("offsets", self.offsets, torch.int64, (n,)),
+                ("sides", self.sides, torch.int32, (n,)),
+                ("scale", self.scale, torch.float32, (n,)),
+                ("model", self.model, torch.uint8, (n,))]
+        for name, t, dt, shp in want:
+            if t is None:
+                continue
+            if t.dtype != dt or t.device != dev or not t.is_contiguous():
+                raise ValueError("%s must be a contiguous %s tensor on %s" % (name, dt, dev))
+            if shp is not None and tuple(t.shape) != shp:
+                raise ValueError("%s must have shape %s" % (name, shp))
+        if (self.offsets is None) != (self.sides is None) and self.offsets is not None:
+            raise ValueError("offsets need sides")
+        if self.sides is None and n and not 4 <= int(self.side0) <= 128:
+            raise ValueError("a uniform batch needs side0 in [4, 128]")
+
     def c_struct(self) -> ShapeBatch:
+        self.validate()
         b = ShapeBatch()
         b.pixels = _ptr(self.pixels)
         b.offset = _ptr(self.offsets)
@@ -288,6 +316,7 @@ def moments(batch: DeviceBatch, rec_in: torch.Tensor, opts: ShapeOpts | None = N
     """shape_moments: returns (rec [n,8], iters, status)."""
     opts = opts or default_opts()
     n, dev = batch.n, batch.device
+    rec_in = _rows(rec_in, n, REC_LEN, "rec_in", dev)
     rec, it, st = _outs(n, dev, ((n, REC_LEN), torch.float32), ((n,), torch.int32),
                         ((n,), torch.int32))
     b = batch.c_struct()
@@ -296,12 +325,25 @@ def moments(batch: DeviceBatch, rec_in: torch.Tensor, opts: ShapeOpts | None = N
     return rec, it, st
 
 
+def _rows(t, n, width, name, device):
+    """A float32 [n, width] input on the batch's device, contiguous (or None)."""
+    if t is None:
+        return None
+    if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != (n, width) \
+            or t.device != device:
+        raise ValueError("%s must be a contiguous float32 [%d, %d] tensor on %s"
+                         % (name, n, width, device))
+    return t
+
+
 def fit_sersic(batch: DeviceBatch, rec: torch.Tensor | None = None,
                p_init: torch.Tensor | None = None, opts: ShapeOpts | None = None,
                want_perr: bool = False):
     """shape_fit_sersic: returns dict(p, chi2, perr, iters, status, sweeps)."""
     opts = opts or default_opts()
     n, dev = batch.n, batch.device
+    rec = _rows(rec, n, REC_LEN, "rec", dev)
+    p_init = _rows(p_init, n, 8, "p_init", dev)
     p, chi2, it, st, sw = _outs(n, dev, ((n, 8), torch.float32), ((n,), torch.float32),
                                 ((n,), torch.int32), ((n,), torch.int32), ((n,), torch.int32))
     perr = torch.empty((n, 8), dtype=torch.float32, device=dev) if want_perr else None
@@ -420,6 +462,7 @@ def star_moments(batch: DeviceBatch, rec: torch.Tensor, profile: int = STAR_GAUS
                  tol: float = 1e-4, max_iter: int = 20):
     """shape_star_moments: returns (out [n,4] = size, beta, I0, r0; iters; status)."""
     n, dev = batch.n, batch.device
+    rec = _rows(rec, n, REC_LEN, "rec", dev)
     out, it, st = _outs(n, dev, ((n, 4), torch.float32), ((n,), torch.int32), ((n,), torch.int32))
     b = batch.c_struct()
     _check(lib.shape_star_moments(C.byref(b), int(profile), _ptr(rec), float(tol), int(max_iter),
@@ -487,6 +530,8 @@ def fit_queue(batch: DeviceBatch, rec: torch.Tensor | None = None,
     opts = opts or default_opts()
     cfg = cfg or queue_cfg()
     n, dev = batch.n, batch.device
+    rec = _rows(rec, n, REC_LEN, "rec", dev)
+    p_init = _rows(p_init, n, 8, "p_init", dev)
     p, chi2, it, st, sw = _outs(n, dev, ((n, 8), torch.float32), ((n,), torch.float32),
                                 ((n,), torch.int32), ((n,), torch.int32), ((n,), torch.int32))
     perr = torch.empty((n, 8), dtype=torch.float32, device=dev) if want_perr else None

@@ -22,7 +22,18 @@ struct QCfg {
   int grid;           // persistent workgroups; 0 = all that fit on the device
 };
 
-size_t queue_workspace_bytes(int64_t n);
+// Workspace layout of the queue form: a 256-byte header, the cursor lines,
+// the (model, side) histogram, the stamp order and one state row per stamp.
+constexpr int kBuckets = 512;
+constexpr int kCursors = 8;
+constexpr int kCursorStride = 32;  // uint32 per cursor line (128 bytes)
+constexpr size_t kCursorBytes = 2 * 2 * kCursors * kCursorStride * 4;
+constexpr size_t kQueueStateBytes = 448;
+__host__ __device__ constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+__host__ __device__ constexpr size_t queue_workspace_bytes(int64_t n) {
+  return 256 + kCursorBytes + align256(kBuckets * 4) + align256((size_t)n * 4) +
+         (size_t)n * kQueueStateBytes;
+}
 hipError_t launch_queue_start(const shape_batch& b, const KOpts& o, void* ws, const float* p_init,
                               const float* rec, const QCfg& cfg, hipStream_t stream);
 hipError_t launch_queue_step(const shape_batch& b, const KOpts& o, void* ws, const QCfg& cfg,

@@ -13,8 +13,9 @@
 //   dl = A_LL^-1 g_L,  chi2* = chi2 - g_L . dl,  s = I0* / I0,
 //   A*_NN = s^2 A_NN,  A*_NL = s A_NL,  g*_N = s (g_N - A_NL dl),  g*_L = 0.
 // The step in the free shape parameters solves (M + lambda diag M) d = g*_N,
-// M = A*_NN - A*_NL (A*_LL)^-1 A*_LN, in FP64 by Cholesky, redundantly in every
-// thread of the team from the same reduced sums (kept in LDS).
+// M = A*_NN - A*_NL (A*_LL)^-1 A*_LN, in FP64 by Gauss-Jordan elimination
+// across the lanes of the team's first wave (lane r holds row r), from the
+// reduced sums kept in LDS.
 #pragma once
 
 #include "sweep.hpp"
@@ -369,7 +370,6 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
                pt[4] <= (double)st.side && pt[6] > 0.0 && __builtin_isfinite(pt[0]) &&
                __builtin_isfinite(pt[1]) && __builtin_isfinite(pt[7]);
       if (MODEL == SHAPE_SERSIC) inside = inside && pt[5] >= 0.2 && pt[5] <= 10.0;
-      if (!inside) L.stt |= SHAPE_ST_AT_BOUND;
 #pragma unroll
       for (int k = 0; k < 8; ++k) W.pt[k] = pt[k];
     }
@@ -421,7 +421,6 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
   const double c2c = W.sums[cur][0];
   int next = cur;
   if (!inside) {
-    L.stt |= SHAPE_ST_AT_BOUND;
     L.lambda *= 10.0;
     if (L.lambda > 1e10) {
       L.stt |= SHAPE_ST_STALLED;
@@ -451,6 +450,22 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
   team_sync<TEAM>();
 }
 
+// Whether the end point lies on the edge of the parameter box: a fitted
+// parameter within a relative 1e-3 of a bound (|e| >= gmax - 1e-3; Re <=
+// 0.1 (1 + 1e-3) or >= side (1 - 1e-3); Sersic n <= 0.2 (1 + 1e-3) or >=
+// 10 (1 - 1e-3)).  Such a minimum lies on the box, not at a stationary point
+// of chi^2; the fit is flagged AT_BOUND.
+template <int MODEL, uint32_t EM>
+__device__ __forceinline__ bool at_box_edge(const double* p, double gmax, int side) {
+  constexpr double m = 1e-3;
+  bool edge = false;
+  if constexpr (has(EM, 2) || has(EM, 3)) edge = edge || p[2] * p[2] + p[3] * p[3] >= (gmax - m) * (gmax - m);
+  if constexpr (has(EM, 4)) edge = edge || p[4] <= 0.1 * (1.0 + m) || p[4] >= side * (1.0 - m);
+  if constexpr (MODEL == SHAPE_SERSIC && has(EM, 5))
+    edge = edge || p[5] <= 0.2 * (1.0 + m) || p[5] >= 10.0 * (1.0 - m);
+  return edge;
+}
+
 // Outputs of a finished (or capped) fit from its state and current sums C:
 // parameters, chi^2, optional sqrt(diag((J^T J / sigma^2)^-1)) over the fitted
 // parameters, iterations, status, sweeps.
@@ -464,6 +479,7 @@ __device__ __forceinline__ void lm_finish(const KOpts& o, const Stamp& st, LmSta
   constexpr uint32_t NL = EM & 0x3Fu;
   const bool valid = !(L.stt & (SHAPE_ST_BAD_INPUT | SHAPE_ST_NONFINITE_INPUT));
   if (valid && !(L.stt & (SHAPE_ST_CONVERGED | SHAPE_ST_STALLED))) L.stt |= SHAPE_ST_MAX_ITER;
+  if (valid && at_box_edge<MODEL, EM>(L.p, o.gmax, st.side)) L.stt |= SHAPE_ST_AT_BOUND;
   if (tid == 0) {
     if (perr) {
       // sigma_p = sigma sqrt(diag(A^-1)) over the fitted parameters, A = J^T J:

@@ -20,16 +20,13 @@ namespace {
 
 // Histogram over (model, side): bucket = side for Sersic, 256 + side for
 // Moffat; stamps that cannot be processed go to bucket 0 (Sersic range).
-constexpr int kBuckets = 512;
+// (kBuckets, kCursors, kCursorStride, kCursorBytes: kernels.hpp)
 constexpr int kChunk = 8;      // stamps per cursor pop
 // Cursors per (model, phase): workgroup g pops from cursor g % kCursors, and
 // cursor c hands out the chunks c, c + kCursors, c + 2 kCursors, ... of the
 // range, so every cursor sees the whole size mix.  Each cursor has its own
 // 128-byte line: pops on different cursors do not contend (consecutive
 // workgroups also land on different XCDs).
-constexpr int kCursors = 8;
-constexpr int kCursorStride = 32;  // uint32 per cursor line
-constexpr size_t kCursorBytes = 2 * 2 * kCursors * kCursorStride * 4;
 
 struct QHeader {
   uint32_t reserved0, reserved1;
@@ -51,6 +48,7 @@ struct QState {
   int32_t done;
 };
 static_assert(sizeof(QState) % 64 == 0, "state rows stay 64-byte aligned");
+static_assert(sizeof(QState) == kQueueStateBytes, "workspace formula and state row agree");
 
 struct QView {
   QHeader* hdr;
@@ -60,7 +58,6 @@ struct QView {
   QState* state;
 };
 
-__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 __host__ __device__ inline QView view(void* ws, int64_t n) {
   char* c = static_cast<char*>(ws);
@@ -404,6 +401,8 @@ hipError_t launch_queue_pass(const shape_batch& b, const KOpts& o, void* ws, con
       hipError_t e = resident_grid(fn, cfg.team, &grid);
       if (e != hipSuccess) return e;
     }
+    // every cursor needs a workgroup of its own to drain it
+    if (grid < kCursors) grid = kCursors;
     void* args[] = {(void*)&b, (void*)&o, &ws, (void*)&p_init, (void*)&rec};
     hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kWave * cfg.team), args, 0, stream);
     if (e != hipSuccess) return e;
@@ -412,11 +411,6 @@ hipError_t launch_queue_pass(const shape_batch& b, const KOpts& o, void* ws, con
 }
 
 }  // namespace
-
-size_t queue_workspace_bytes(int64_t n) {
-  return 256 + kCursorBytes + align256(kBuckets * 4) + align256((size_t)n * 4) +
-         (size_t)n * sizeof(QState);
-}
 
 hipError_t launch_queue_start(const shape_batch& b, const KOpts& o, void* ws, const float* p_init,
                               const float* rec, const QCfg& cfg, hipStream_t stream) {

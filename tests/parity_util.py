@@ -1,13 +1,48 @@
-"""Helpers for the GPU-vs-oracle parity tests."""
+"""Helpers for the GPU-vs-oracle parity tests.
+
+The fit's parity rule (stamps are classed by their fit status):
+  * interior: CONVERGED and not AT_BOUND (the fit ended at a stationary point
+    of chi^2 inside the parameter box);
+  * bound: CONVERGED | AT_BOUND (a constrained minimum on the box edge);
+  * max_iter, stalled, other.
+On stamps interior on both sides the GPU must meet the bars (|dx|, |dy| <=
+1e-3 px, |de| <= 1e-4, relative 1e-3 on Re and n), its amplitudes must agree
+(relative 1e-3, or 1e-2 of the standard error where that is looser), its chi^2
+must equal the oracle's chi^2 at the GPU's parameters (relative 1e-6 plus the
+effect of a 1e-6 relative error of the FP32 render, which grows with S/N) and its
+sigma_p the oracle's at the GPU's parameters within the rounding of FP32 J^T J
+propagated through the inverse (see sigma_tolerance).  A stamp outside the bars
+must be an equally good minimum: the oracle's chi^2 at the GPU's parameters is
+no larger than at its own (relative 1e-6) and the FP64 Newton step from the
+GPU's parameters is below 1e-2 of every standard error.  The same validation
+applies where the GPU ends in the interior and the oracle on the box.
+Where the GPU ends on the box and the oracle does not, the library has flagged
+the fit itself; such stamps are counted, as are the MAX_ITER / STALLED ones.
+"""
 import numpy as np
 
 import oracle
 
-# Parity bars (GPU vs FP64 oracle, stamps where both report CONVERGED):
-# |dx|, |dy| <= 1e-3 px, |de| <= 1e-4, relative 1e-3 on Re and n.
+# Parity bars (GPU vs FP64 oracle on stamps both sides fit to the interior).
 BAR_X = 1e-3
 BAR_E = 1e-4
 BAR_REL = 1e-3
+# amplitudes: relative 1e-3, or 1e-2 of the standard error
+BAR_AMP_REL = 1e-3
+BAR_AMP_SIGMA = 1e-2
+# chi^2 of the GPU against the oracle's chi^2 at the GPU's parameters: the
+# FP32 output rounds by 6e-8, and a render with relative error RENDER_EPS per
+# pixel moves chi^2 by at most 2 RENDER_EPS sqrt(sum (m/sigma)^2) sqrt(chi^2)
+# (Cauchy-Schwarz), which dominates at high S/N
+BAR_CHI2_SAME_POINT = 1e-6
+RENDER_EPS = 1e-6
+# validation of an alternative minimum
+ALT_CHI2_SLACK = 1e-6
+ALT_NEWTON_SIGMA = 1e-2
+# relative accuracy of the library's FP32 J^T J entries against
+# sqrt(A_ii A_jj): FP32-rounded Jacobian products summed in FP32 over at most
+# 256 pixels per lane, then reduced (a bound, about 25x the largest error seen)
+JTJ_EPS = 1e-5
 
 
 def run_gpu(shape, batch, opts=None, device="cuda:0"):
@@ -32,8 +67,159 @@ def oracle_opts_like(gpu_opts, **kw):
     return o
 
 
-def compare(gpu, ref, free_mask=0xFF, label=""):
-    """Return a dict of parity statistics (GPU vs oracle)."""
+def fit_class(status):
+    """Status class per stamp: 'interior', 'bound', 'max_iter', 'stalled' or 'other'."""
+    st = np.asarray(status).astype(np.uint32)
+    conv = (st & oracle.CONVERGED) != 0
+    bound = (st & oracle.AT_BOUND) != 0
+    out = np.full(st.shape, "other", dtype=object)
+    out[(st & oracle.STALLED) != 0] = "stalled"
+    out[(st & oracle.MAX_ITER) != 0] = "max_iter"
+    out[conv & bound] = "bound"
+    out[conv & ~bound] = "interior"
+    bad = (st & (oracle.BAD_INPUT | oracle.NONFINITE_INPUT)) != 0
+    out[bad] = "invalid"
+    return out
+
+
+def _free(free_mask, kind):
+    return [k for k in range(8) if (free_mask >> k) & 1 and not (kind == oracle.MOFFAT and k == 5)]
+
+
+def _tri(k, l):
+    if k > l:
+        k, l = l, k
+    return k * 8 - k * (k - 1) // 2 + (l - k)
+
+
+def _normal(jtj, idx):
+    return np.array([[jtj[_tri(i, j)] for j in idx] for i in idx])
+
+
+def sigma_tolerance(A):
+    """Tolerance on the relative error of sqrt(diag(A^-1)) when every entry of
+    A carries a relative error JTJ_EPS of sqrt(A_ii A_jj): the first-order
+    change of (A^-1)_kk is bounded by eps (sum_i |(A^-1)_ki| sqrt(A_ii))^2, so
+    that of sigma_k by half that over (A^-1)_kk; plus 1e-4 for the end point."""
+    Ai = np.linalg.inv(A)
+    d = np.sqrt(np.diag(A))
+    B = (np.abs(Ai) @ d) ** 2 / np.diag(Ai)
+    return 1e-4 + 0.5 * JTJ_EPS * B
+
+
+def validate_minimum(img, sigma, kind, p_gpu, chi2_ref, idx):
+    """Whether p_gpu is a minimum of the full chi^2 at least as good as the
+    oracle's: returns (ok, chi2 at p_gpu relative to chi2_ref - 1, largest
+    Newton step in standard errors)."""
+    c, g, jtj = oracle.chi2(img, sigma, p_gpu, kind, want_grad=True)
+    A = _normal(jtj, idx)
+    try:
+        Ai = np.linalg.inv(A)
+    except np.linalg.LinAlgError:
+        return False, float("nan"), float("inf")
+    step = -0.5 * Ai @ g[idx]
+    newton = float(np.max(np.abs(step) / np.sqrt(np.diag(Ai))))
+    worse = float(c / chi2_ref - 1.0)
+    ok = np.isfinite(c) and worse <= ALT_CHI2_SLACK and newton <= ALT_NEWTON_SIGMA
+    return bool(ok), worse, newton
+
+
+def _pct(v):
+    v = np.asarray(v, np.float64)
+    v = v[np.isfinite(v)]
+    if v.size == 0:
+        return None
+    return [float(np.percentile(v, 50)), float(np.percentile(v, 99)), float(v.max())]
+
+
+def fit_parity(gpu, ref, batch, free_mask=0xFF, label="", max_checks=None):
+    """GPU fit against the oracle's by the rule in the module docstring.
+    Returns (stats, failures): failures lists the stamps that break the rule."""
+    pix = batch.dequantised_f64()
+    cg, co = fit_class(gpu["status"][:, 2]), fit_class(ref["status"][:, 2])
+    pg, po = gpu["p"].astype(np.float64), ref["p"]
+    n = len(cg)
+    st = {"n": n}
+    for c in ("interior", "bound", "max_iter", "stalled", "other", "invalid"):
+        st["gpu_" + c] = int((cg == c).sum())
+        st["oracle_" + c] = int((co == c).sum())
+    st["class_agree"] = float((cg == co).mean()) if n else 1.0
+    ended = np.isin(cg, ("interior", "bound")) & np.isin(co, ("interior", "bound"))
+    st["class_agree_where_both_ended"] = float((cg[ended] == co[ended]).mean()) if ended.any() else 1.0
+    st["both_max_iter"] = int(((cg == "max_iter") & (co == "max_iter")).sum())
+    st["both_stalled"] = int(((cg == "stalled") & (co == "stalled")).sum())
+    st["gpu_bound_oracle_interior"] = int(((cg == "bound") & (co == "interior")).sum())
+    failures = []
+    both = np.flatnonzero((cg == "interior") & (co == "interior"))
+    gi_ob = np.flatnonzero((cg == "interior") & (co == "bound"))
+    st["both_interior"] = len(both)
+    devs = {k: [] for k in ("dx", "de", "rel_re", "rel_n", "rel_i0", "rel_sky")}
+    zs, chi2_same, chi2_own, sig_rel, sig_ratio = [], [], [], [], []
+    alt, n_alt = [], 0
+    todo = list(both) if max_checks is None else list(both[:max_checks])
+    for s in todo + list(gi_ob):
+        side = int(batch.sides[s])
+        img = pix[batch.offsets[s]:batch.offsets[s] + side * side].reshape(side, side)
+        kind = int(batch.model[s])
+        sig = float(batch.sigma[s])
+        idx = _free(free_mask, kind)
+        d = np.abs(pg[s] - po[s])
+        rel = np.abs(pg[s] / po[s] - 1)
+        in_bars = (d[:2].max() <= BAR_X and d[2:4].max() <= BAR_E and
+                   all(rel[k] <= BAR_REL for k in (4, 5) if k in idx))
+        if co[s] == "bound" or not in_bars:
+            ok, worse, newton = validate_minimum(img, sig, kind, pg[s], ref["chi2"][s], idx)
+            alt.append(dict(stamp=int(s), oracle_class=co[s], chi2_rel=worse, newton_sigma=newton,
+                            ok=ok))
+            if ok:
+                n_alt += 1
+            else:
+                failures.append(("alternative minimum not validated", int(s), worse, newton))
+            continue
+        c_at, _, jtj = oracle.chi2(img, sig, pg[s], kind, want_grad=True)
+        A = _normal(jtj, idx)
+        sig_at = np.sqrt(np.diag(np.linalg.inv(A)))
+        tol = sigma_tolerance(A)
+        for name, v in (("dx", d[:2].max()), ("de", d[2:4].max()), ("rel_re", rel[4]),
+                        ("rel_n", rel[5] if 5 in idx else 0.0), ("rel_i0", rel[6]),
+                        ("rel_sky", rel[7])):
+            devs[name].append(v)
+        # amplitudes (the oracle's own standard errors)
+        for k in (6, 7):
+            if k in idx and not (rel[k] <= BAR_AMP_REL or d[k] <= BAR_AMP_SIGMA * ref["perr"][s, k]):
+                failures.append(("amplitude %d" % k, int(s), float(rel[k]),
+                                 float(d[k] / ref["perr"][s, k])))
+        z = d[idx] / ref["perr"][s, idx]
+        zs.append(z.max())
+        r_same = abs(float(gpu["chi2"][s]) / c_at - 1)
+        chi2_same.append(r_same)
+        chi2_own.append(abs(float(gpu["chi2"][s]) / ref["chi2"][s] - 1))
+        m = oracle.model(side, pg[s], kind)
+        tol_c2 = BAR_CHI2_SAME_POINT + 2 * RENDER_EPS * np.sqrt(np.sum((m / sig) ** 2) / c_at)
+        if not r_same <= tol_c2:
+            failures.append(("chi2 at the GPU's parameters", int(s), r_same, tol_c2))
+        if "perr" in gpu and gpu["perr"] is not None:
+            e = np.abs(gpu["perr"][s, idx] / sig_at - 1)
+            sig_rel.append(e.max())
+            sig_ratio.append(float(np.max(e / tol)))
+            if not np.all(e <= tol):
+                failures.append(("sigma_p", int(s), float(e.max()), float(np.max(e / tol))))
+    st["validated_alternative_minima"] = n_alt
+    st["gpu_interior_oracle_bound"] = len(gi_ob)
+    st["deviation_p50_p99_max"] = {k: _pct(v) for k, v in devs.items()}
+    st["dp_over_sigma_p50_p99_max"] = _pct(zs)
+    st["chi2_rel_same_point_p50_p99_max"] = _pct(chi2_same)
+    st["chi2_rel_oracle_p50_p99_max"] = _pct(chi2_own)
+    st["sigma_rel_p50_p99_max"] = _pct(sig_rel)
+    st["sigma_err_over_tolerance_max"] = max(sig_ratio) if sig_ratio else None
+    st["alternatives"] = alt[:20]
+    return st, failures
+
+
+def compare(gpu, ref, free_mask=0xFF, label="", batch=None):
+    """Stage statistics (centroid, moments) and the fit's parity (GPU vs
+    oracle).  Returns a dict; r['fit_failures'] lists the stamps that break
+    the fit's rule."""
     st_g, st_o = gpu["status"].astype(np.uint32), ref["status"]
     conv = lambda st, k: (st[:, k] & oracle.CONVERGED) != 0
     out = {}
@@ -60,24 +246,19 @@ def compare(gpu, ref, free_mask=0xFF, label=""):
     out["size_rel"] = float(np.abs(mg[both1, 8][fin] / mo[both1, 6][fin] - 1).max()) if fin.any() else 0.0
     out["status1_agree"] = float((st_g[:, 1] == st_o[:, 1]).mean())
     # fit
-    both2 = conv(st_g, 2) & conv(st_o, 2)
-    pg, po = gpu["p"], ref["p"]
-    out["fit_gpu_conv"] = int(conv(st_g, 2).sum())
-    out["fit_oracle_conv"] = int(conv(st_o, 2).sum())
-    out["fit_both"] = int(both2.sum())
-    if both2.any():
-        d = np.abs(pg[both2] - po[both2])
-        rel = np.abs(pg[both2] / po[both2] - 1)
-        out["fit_dxy"] = float(d[:, :2].max())
-        out["fit_de"] = float(d[:, 2:4].max())
-        out["fit_re_rel"] = float(rel[:, 4].max())
-        out["fit_n_rel"] = float(rel[:, 5].max())
-        out["fit_i0_rel"] = float(rel[:, 6].max())
-        out["fit_sky_rel"] = float(rel[:, 7].max())
-        out["fit_x_ok"] = float((d[:, :2].max(1) <= BAR_X).mean())
-        out["fit_e_ok"] = float((d[:, 2:4].max(1) <= BAR_E).mean())
-        out["fit_rel_ok"] = float((rel[:, 4:6].max(1) <= BAR_REL).mean())
-        worst = np.argsort(-rel[:, 4:6].max(1))[:3]
-        out["worst_idx"] = [int(i) for i in np.flatnonzero(both2)[worst]]
-    print(label, {k: (round(v, 7) if isinstance(v, float) else v) for k, v in out.items()})
+    fit, failures = fit_parity(gpu, ref, batch, free_mask, label)
+    out.update({"fit_" + k: v for k, v in fit.items()})
+    out["fit_failures"] = failures
+    show = {k: v for k, v in out.items() if k not in ("fit_alternatives",)}
+    print(label, {k: (round(v, 7) if isinstance(v, float) else v) for k, v in show.items()})
     return out
+
+
+def check_fit(r, min_interior_frac, max_gpu_bound_frac=2e-3):
+    """The fit's rule: no failing stamp; enough stamps fit to the interior;
+    few stamps where the GPU ends on the box (and says so) but the oracle
+    finds an interior minimum.  (The GPU's trial cap is 30, the oracle's 200,
+    so MAX_ITER is compared by count, not asserted.)"""
+    assert not r["fit_failures"], r["fit_failures"][:10]
+    assert r["fit_gpu_interior"] >= min_interior_frac * r["n"], r
+    assert r["fit_gpu_bound_oracle_interior"] <= max(1, max_gpu_bound_frac * r["n"]), r

@@ -130,21 +130,19 @@ def test_f16_frames(shape):
 def test_frames_to_fitted_objects(shape):
     """Cut-outs feed the per-object pipeline: fit parity on them as on stamps."""
     import torch
-    from parity_util import BAR_E, BAR_REL, BAR_X
+    from parity_util import check_fit, fit_parity
     f = synth.make_frames(32)
     fr, g = _gpu_detect(shape, f.pixels)
     db = shape.frame_cut(fr, torch.from_numpy(g["box"]).cuda(), torch.from_numpy(f.sigma).cuda())
-    out = shape.pipeline(db)
+    out = shape.pipeline(db, want_perr=True)
     torch.cuda.synchronize()
     pix = db.pixels.cpu().numpy()
     b = synth.Batch("frames", pix, db.offsets.cpu().numpy(), db.sides.cpu().numpy(), f.sigma,
                     np.zeros(f.n, np.uint8), f.truth, None)
     ref = oracle.pipeline(b, oracle.opts())
-    st = out["status"].cpu().numpy().astype(np.uint32)
-    both = ((st[:, 2] & 1) != 0) & ((ref["status"][:, 2] & 1) != 0)
-    assert both.sum() >= 0.8 * f.n
-    p = out["p"].cpu().numpy().astype(np.float64)[both]
-    q = ref["p"][both]
-    ok = (np.abs(p[:, :2] - q[:, :2]).max(1) <= BAR_X) & (np.abs(p[:, 2:4] - q[:, 2:4]).max(1) <= BAR_E) \
-        & (np.abs(p[:, 4:6] / q[:, 4:6] - 1).max(1) <= BAR_REL)
-    assert ok.mean() >= 0.95
+    gpu = {k: v.cpu().numpy() for k, v in out.items() if hasattr(v, "cpu")}
+    st, failures = fit_parity(gpu, ref, b, 0xFF, "frames")
+    print(st)
+    r = {"fit_" + k: v for k, v in st.items()}
+    r.update(n=st["n"], fit_failures=failures)
+    check_fit(r, 0.8)

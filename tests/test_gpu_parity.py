@@ -1,14 +1,18 @@
 """GPU parity: the HIP stages against the FP64 oracle on seeded stamps.
 
-Bars (stamps where both sides report CONVERGED): |dx|, |dy| <= 1e-3 px,
-|de| <= 1e-4, relative 1e-3 on Re and n.  Inputs are the synthetic
-workloads of the generator (the paper's simulation recipe, Sec. 4.1)."""
+Stages: centroid and moments within |dx|, |dy| <= 1e-3 px and |de| <= 1e-4 on
+stamps both sides converge.  Fit: the rule of parity_util (bars on stamps both
+sides fit to the interior of the parameter box, chi^2, sigma_p and amplitudes
+checked there, every disagreement validated as an equally good minimum of the
+oracle's chi^2).  Inputs are the synthetic workloads of the generator (the
+paper's simulation recipe, Sec. 4.1)."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from parity_util import BAR_E, BAR_REL, BAR_X, compare, oracle_opts_like, run_gpu
+from parity_util import (BAR_E, BAR_REL, BAR_X, check_fit, compare, fit_class, oracle_opts_like,
+                         run_gpu, validate_minimum)
 
 pytestmark = pytest.mark.gpu
 
@@ -21,12 +25,10 @@ def shape():
     return shape
 
 
-def _check_bars(r, min_both_frac, min_ok=1.0):
-    assert r["fit_both"] >= min_both_frac * r["n"], r
+def _check_stages(r):
     assert r["centroid_dxy"] <= BAR_X, r
     assert r["moments_dxy"] <= BAR_X and r["moments_de"] <= BAR_E, r
     assert r["size_rel"] <= 1e-3 and r["size_defined_agree"] >= 0.99, r
-    assert r["fit_x_ok"] >= min_ok and r["fit_e_ok"] >= min_ok and r["fit_rel_ok"] >= min_ok, r
 
 
 def test_gaussian_workload_4_params(shape):
@@ -35,10 +37,11 @@ def test_gaussian_workload_4_params(shape):
     o = shape.default_opts(free_mask=shape.MASK_SIZE)
     g = run_gpu(shape, b, o)
     ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
-    r = compare(g, ref, 0xF0, "plain32")
+    r = compare(g, ref, 0xF0, "plain32", batch=b)
     assert r["r50_rel"] < 1e-5 and r["sigw_rel"] < 1e-5
     assert r["status0_agree"] > 0.99 and r["status1_agree"] > 0.99
-    _check_bars(r, 0.98)
+    _check_stages(r)
+    check_fit(r, 0.98)
     # the centre and ellipticity are held in the 4-parameter fit
     conv = (g["status"][:, 2] & shape.ST_CONVERGED) != 0
     np.testing.assert_array_equal(g["p"][conv, :4], g["moments"][conv, :4])
@@ -52,8 +55,9 @@ def test_unprofiled_4_params(shape):
     o = shape.default_opts(free_mask=shape.MASK_SIZE, linear_init=0)
     g = run_gpu(shape, b, o)
     ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
-    r = compare(g, ref, 0xF0, "plain32 unprofiled")
-    _check_bars(r, 0.95)
+    r = compare(g, ref, 0xF0, "plain32 unprofiled", batch=b)
+    _check_stages(r)
+    check_fit(r, 0.95)
     gp = run_gpu(shape, b, shape.default_opts(free_mask=shape.MASK_SIZE))
     both = ((g["status"][:, 2] & gp["status"][:, 2] & shape.ST_CONVERGED) != 0)
     assert both.mean() > 0.95
@@ -68,8 +72,9 @@ def test_sersic_workloads_8_params(shape, workload, count):
     o = shape.default_opts()
     g = run_gpu(shape, b, o)
     ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
-    r = compare(g, ref, 0xFF, workload)
-    _check_bars(r, 0.85, min_ok=0.995)
+    r = compare(g, ref, 0xFF, workload, batch=b)
+    _check_stages(r)
+    check_fit(r, 0.85)
 
 
 def test_standard_error_stop_only_adds_convergence(shape):
@@ -82,7 +87,9 @@ def test_standard_error_stop_only_adds_convergence(shape):
     g, g0 = run_gpu(shape, b, o), run_gpu(shape, b, o0)
     ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
     for gg, label in ((g, "tol_sigma default"), (g0, "tol_sigma 0")):
-        _check_bars(compare(gg, ref, 0xFF, label), 0.85, min_ok=0.995)
+        r = compare(gg, ref, 0xFF, label, batch=b)
+        _check_stages(r)
+        check_fit(r, 0.85)
     c, c0 = (((x["status"][:, 2] & shape.ST_CONVERGED) != 0) for x in (g, g0))
     assert np.all(c[c0])
     assert g["iters"][c0, 2].mean() <= g0["iters"][c0, 2].mean()
@@ -94,8 +101,9 @@ def test_fp16_storage(shape):
     o = shape.default_opts()
     g = run_gpu(shape, b, o)
     ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
-    r = compare(g, ref, 0xFF, "sersic64h")
-    _check_bars(r, 0.85, min_ok=0.995)
+    r = compare(g, ref, 0xFF, "sersic64h", batch=b)
+    _check_stages(r)
+    check_fit(r, 0.85)
 
 
 def test_uneven_sizes_and_moffat_stars(shape):
@@ -103,8 +111,9 @@ def test_uneven_sizes_and_moffat_stars(shape):
     o = shape.default_opts()
     g = run_gpu(shape, b, o)
     ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
-    r = compare(g, ref, 0xFF, "uneven")
-    _check_bars(r, 0.8, min_ok=0.99)
+    r = compare(g, ref, 0xFF, "uneven", batch=b)
+    _check_stages(r)
+    check_fit(r, 0.8)
     stars = b.model == 1
     assert ((g["status"][stars, 2] & shape.ST_CONVERGED) != 0).mean() > 0.8
 
@@ -181,8 +190,9 @@ def test_full_size_sampled(shape):
                       b.model[idx], b.truth[idx], None)
     ref = oracle.pipeline(sub, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
     gs = {k: v[idx] for k, v in g.items() if isinstance(v, np.ndarray) and v.shape[:1] == (b.n,)}
-    r = compare(gs, ref, 0xFF, "sersic64 full, sampled")
-    _check_bars(r, 0.85, min_ok=0.99)
+    r = compare(gs, ref, 0xFF, "sersic64 full, sampled", batch=sub)
+    _check_stages(r)
+    check_fit(r, 0.85)
     conv = (g["status"][:, 2] & shape.ST_CONVERGED) != 0
     print("full-size convergence fraction %.4f" % conv.mean())
     assert conv.mean() > 0.85
@@ -212,9 +222,20 @@ def test_register_and_memory_paths_agree(shape, workload):
         assert np.abs(r[stage][ok, :2] - m[stage][ok, :2]).max() <= BAR_X
         if stage == "moments":
             assert np.abs(r[stage][ok, 2:4] - m[stage][ok, 2:4]).max() <= BAR_E
-    both = ((r["status"][:, 2] & m["status"][:, 2] & shape.ST_CONVERGED) != 0)
+    both = (fit_class(r["status"][:, 2]) == "interior") & (fit_class(m["status"][:, 2]) == "interior")
     assert both.mean() > 0.85
-    assert np.abs(r["p"][both, :2] - m["p"][both, :2]).max() <= BAR_X
-    assert np.abs(r["p"][both, 2:4] - m["p"][both, 2:4]).max() <= BAR_E
-    rel = np.abs(r["p"][both, 4:6] / m["p"][both, 4:6] - 1).max(axis=1)
-    assert (rel <= BAR_REL).mean() >= 0.995
+    mask = 0xF0 if workload == "plain32" else 0xFF
+    pr, pm = r["p"].astype(np.float64), m["p"].astype(np.float64)
+    ok = (np.abs(pr[:, :2] - pm[:, :2]).max(1) <= BAR_X) & \
+         (np.abs(pr[:, 2:4] - pm[:, 2:4]).max(1) <= BAR_E) & \
+         (np.abs(pr[:, 4:6] / pm[:, 4:6] - 1).max(1) <= BAR_REL)
+    # where the two codings part, each must have ended at a stationary point
+    # of the oracle's chi^2 (two minima of a flat valley)
+    pix = b.dequantised_f64()
+    idx = [k for k in range(8) if (mask >> k) & 1]
+    for s in np.flatnonzero(both & ~ok):
+        img = pix[b.offsets[s]:b.offsets[s] + b.sides[s] ** 2].reshape(b.sides[s], b.sides[s])
+        sig = float(b.sigma[s])
+        for pp in (pr[s], pm[s]):
+            c = oracle.chi2(img, sig, pp)
+            assert validate_minimum(img, sig, 0, pp, c, idx)[0], s

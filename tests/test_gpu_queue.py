@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from parity_util import compare, oracle_opts_like
+from parity_util import check_fit, compare, oracle_opts_like
 
 pytestmark = pytest.mark.gpu
 
@@ -71,7 +71,8 @@ def test_queue_uneven_parity(shape, team, min_side):
     db = shape.DeviceBatch.from_host(b, "cuda:0")
     o = shape.default_opts()
     rec = _moments(shape, db, o)
-    q = shape.fit_queue(db, rec=rec, opts=o, cfg=shape.queue_cfg(team=team, team_min_side=min_side))
+    q = shape.fit_queue(db, rec=rec, opts=o, cfg=shape.queue_cfg(team=team, team_min_side=min_side),
+                        want_perr=True)
     import torch
     torch.cuda.synchronize()
     g = _np(q)
@@ -79,9 +80,8 @@ def test_queue_uneven_parity(shape, team, min_side):
     g["moments"] = rec.cpu().numpy()
     g["status"] = np.stack([shape.centroid(db, o)[2].cpu().numpy(), shape.moments(db, shape.centroid(db, o)[0], o)[2].cpu().numpy(), g["status"]], 1)
     ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
-    r = compare(g, ref, 0xFF, "queue team=%d" % team)
-    assert r["fit_both"] >= 0.8 * r["n"]
-    assert r["fit_x_ok"] >= 0.99 and r["fit_e_ok"] >= 0.99 and r["fit_rel_ok"] >= 0.99
+    r = compare(g, ref, 0xFF, "queue team=%d" % team, batch=b)
+    check_fit(r, 0.8)
 
 
 def test_queue_caps_and_empty(shape):

@@ -67,6 +67,21 @@ def test_noiseless_recovery_8_params(truth):
     assert r["chi2"] < 1e-12
 
 
+@pytest.mark.parametrize("n_true,edge", [(10.0, True), (4.0, False), (0.2, True), (0.3, False)])
+def test_fit_ending_on_the_box_is_flagged(n_true, edge):
+    """A minimum on the edge of the parameter box (here a noiseless source
+    whose index is the bound itself) is flagged AT_BOUND; one a little inside
+    is not.  The inner one is recovered exactly; the edge one is approached
+    from inside (trials past the bound are rejected) to within the margin."""
+    truth = np.array([23.7, 24.2, 0.21, -0.13, 3.2, n_true, 500.0, 10.0])
+    img = _noiseless(truth, 48)
+    p0 = truth * np.array([1, 1, 0.9, 1.1, 1.1, 0.95 if n_true > 1 else 1.2, 1, 1])
+    r = oracle.fit(img, 1.0, p0, o=oracle.opts(tol_lm=1e-10, max_iter_lm=300))
+    assert r["status"] & oracle.CONVERGED
+    assert bool(r["status"] & oracle.AT_BOUND) == edge, hex(r["status"])
+    np.testing.assert_allclose(r["p"][5], n_true, rtol=1e-3 if edge else 1e-6)
+
+
 def test_noiseless_recovery_moffat():
     truth = np.array([31.2, 30.7, 0.06, -0.04, 2.4, 3.0, 900.0, 10.0])
     img = _noiseless(truth, 64, oracle.MOFFAT)

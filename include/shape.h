@@ -36,7 +36,8 @@
  *     out of range, sigma <= 0, offset outside the pixel buffer, NaN/Inf
  *     pixels) never fail the call: they set that stamp's status bits and its
  *     outputs to NaN.  n = 0 is a no-op returning SHAPE_OK.
- *   - Reentrant; no global mutable state.
+ *   - Reentrant; no global mutable state except the static workspace of
+ *     shape_fit_queue_static (see there).
  */
 #ifndef SHAPE_H
 #define SHAPE_H
@@ -292,6 +293,28 @@ int shape_queue_graph_create(const shape_batch* batch, const shape_opts* opts,
                              shape_queue_graph** graph);
 int shape_queue_graph_launch(shape_queue_graph* graph, void* stream);
 int shape_queue_graph_destroy(shape_queue_graph* graph);
+
+/*
+ * The work-queue fit in one call, with no allocation: for callers that cannot
+ * allocate device memory (code under hipGraph/stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same inputs and outputs as
+ * shape_fit_sersic plus the queue configuration; it runs shape_queue_start,
+ * max_iter_lm steps (a step skips the stamps that are done) and
+ * shape_queue_finish, with the workspace in a static device array of the
+ * library (queue workspace of SHAPE_STATIC_MAX_STAMPS stamps, about 29 MB,
+ * held on every device the library runs on until the process ends).  The
+ * results equal those of the three calls with a caller's workspace.
+ *   n > SHAPE_STATIC_MAX_STAMPS returns SHAPE_ENOMEM before any work.
+ * The array is shared by every call on a device: calls that overlap on one
+ * device (several streams or host threads) race and must be serialised by
+ * the caller.  Its device address is looked up on the first call on each
+ * device (hipGetSymbolAddress); make a first call outside stream capture.
+ */
+#define SHAPE_STATIC_MAX_STAMPS 65536
+int shape_fit_queue_static(const shape_batch* batch, const shape_opts* opts,
+                           const shape_queue_cfg* cfg, const float* p_init, const float* rec,
+                           float* p_out, float* chi2, float* perr, int32_t* iters,
+                           uint32_t* status, int32_t* sweeps, void* stream);
 
 /* ------------------------------------------------------------------------
  * Front end on whole frames (Sec. 4.1, the paragraph on the starting point):

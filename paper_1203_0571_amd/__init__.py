@@ -43,6 +43,7 @@ ST_LOST = 0x200
 REC_LEN = 9
 MASK_ALL = 0xFF
 MASK_SIZE = 0xF0
+STATIC_MAX_STAMPS = 65536   # SHAPE_STATIC_MAX_STAMPS: shape_fit_queue_static's limit
 
 
 class ShapeBatch(C.Structure):
@@ -140,9 +141,10 @@ def _load():
     lib.shape_queue_graph_create.argtypes = [bp, op, qp, vp, C.c_size_t, C.POINTER(C.c_void_p)]
     lib.shape_queue_graph_launch.argtypes = [vp, vp]
     lib.shape_queue_graph_destroy.argtypes = [vp]
+    lib.shape_fit_queue_static.argtypes = [bp, op, qp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     for f in ("shape_queue_default_cfg", "shape_queue_workspace_bytes", "shape_queue_start",
               "shape_queue_step", "shape_queue_finish", "shape_queue_graph_create",
-              "shape_queue_graph_launch", "shape_queue_graph_destroy"):
+              "shape_queue_graph_launch", "shape_queue_graph_destroy", "shape_fit_queue_static"):
         getattr(lib, f).restype = C.c_int
     return lib
 
@@ -561,6 +563,33 @@ def fit_queue(batch: DeviceBatch, rec: torch.Tensor | None = None,
                                   _ptr(chi2), _ptr(perr), _ptr(it), _ptr(st), _ptr(sw),
                                   _stream(dev)), "shape_queue_finish")
     return dict(p=p, chi2=chi2, perr=perr, iters=it, status=st, sweeps=sw, steps=steps)
+
+
+def fit_queue_static(batch: DeviceBatch, rec: torch.Tensor | None = None,
+                     p_init: torch.Tensor | None = None, opts: ShapeOpts | None = None,
+                     cfg: QueueCfg | None = None, out: dict | None = None,
+                     want_perr: bool = False):
+    """shape_fit_queue_static: the work-queue fit in one call on the library's
+    static workspace (at most STATIC_MAX_STAMPS stamps).  With `out` (a dict of
+    preallocated p, chi2, iters, status and optional perr, sweeps tensors) the
+    call allocates nothing on the device."""
+    opts = opts or default_opts()
+    cfg = cfg or queue_cfg()
+    n, dev = batch.n, batch.device
+    rec = _rows(rec, n, REC_LEN, "rec", dev)
+    p_init = _rows(p_init, n, 8, "p_init", dev)
+    if out is None:
+        p, chi2, it, st, sw = _outs(n, dev, ((n, 8), torch.float32), ((n,), torch.float32),
+                                    ((n,), torch.int32), ((n,), torch.int32), ((n,), torch.int32))
+        perr = torch.empty((n, 8), dtype=torch.float32, device=dev) if want_perr else None
+        out = dict(p=p, chi2=chi2, perr=perr, iters=it, status=st, sweeps=sw)
+    b = batch.c_struct()
+    _check(lib.shape_fit_queue_static(C.byref(b), C.byref(opts), C.byref(cfg), _ptr(p_init),
+                                      _ptr(rec), _ptr(out["p"]), _ptr(out["chi2"]),
+                                      _ptr(out.get("perr")), _ptr(out["iters"]),
+                                      _ptr(out["status"]), _ptr(out.get("sweeps")), _stream(dev)),
+           "shape_fit_queue_static")
+    return out
 
 
 def pipeline(batch: DeviceBatch, opts: ShapeOpts | None = None, want_perr: bool = False):

@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libshape.so")
-SOURCES = ["api.hip", "centroid.hip", "moments.hip", "fit.hip", "adjoint.hip", "queue.hip", "stars.hip", "frames.hip"]
+SOURCES = ["api.hip", "centroid.hip", "moments.hip", "fit.hip", "adjoint.hip", "queue.hip", "stars.hip", "frames.hip", "noalloc.hip"]
 ARCH = os.environ.get("SHAPE_OFFLOAD_ARCH", "gfx950")
 
 

@@ -263,6 +263,19 @@ int shape_queue_finish(const shape_batch* b, const shape_opts* o, void* ws, size
                                       (hipStream_t)stream));
 }
 
+int shape_fit_queue_static(const shape_batch* b, const shape_opts* o, const shape_queue_cfg* c,
+                           const float* p_init, const float* rec, float* p_out, float* chi2,
+                           float* perr, int32_t* iters, uint32_t* status, int32_t* sweeps,
+                           void* stream) {
+  if (b && b->n > SHAPE_STATIC_MAX_STAMPS) return SHAPE_ENOMEM;
+  // the workspace checks of check_queue are met by the static array
+  int rc = check_queue(b, o, c, reinterpret_cast<void*>(1), static_queue_scratch_bytes());
+  if (rc != SHAPE_OK || b->n == 0) return rc;
+  if ((!p_init && !rec) || !p_out || !chi2 || !iters || !status) return SHAPE_EINVAL;
+  return from_hip(launch_fit_queue_static(*b, kopts(o), p_init, rec, qcfg(c), p_out, chi2, perr,
+                                          iters, status, sweeps, (hipStream_t)stream));
+}
+
 struct shape_queue_graph {
   hipGraph_t graph;
   hipGraphExec_t exec;

@@ -42,6 +42,14 @@ hipError_t launch_queue_finish(const shape_batch& b, const KOpts& o, void* ws, f
                                float* chi2, float* perr, int32_t* iters, uint32_t* status,
                                int32_t* sweeps, hipStream_t stream);
 
+// The queue fit on the library's static workspace (at most
+// SHAPE_STATIC_MAX_STAMPS stamps); no allocation.
+size_t static_queue_scratch_bytes();
+hipError_t launch_fit_queue_static(const shape_batch& b, const KOpts& o, const float* p_init,
+                                   const float* rec, const QCfg& cfg, float* p_out, float* chi2,
+                                   float* perr, int32_t* iters, uint32_t* status,
+                                   int32_t* sweeps, hipStream_t stream);
+
 hipError_t launch_stars(const shape_batch& b, int profile, const float* rec, double tol,
                         int max_iter, float* out, int32_t* iters, uint32_t* status,
                         hipStream_t stream);

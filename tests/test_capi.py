@@ -168,6 +168,27 @@ def test_queue_argument_errors(shape):
     assert L.shape_queue_step(C.byref(e), C.byref(o), C.byref(c), None, 0, None) == shape.OK
 
 
+def test_static_queue_fit_limits(shape):
+    """shape_fit_queue_static: more stamps than its static workspace holds is
+    SHAPE_ENOMEM, checked before anything touches a device; bad arguments are
+    SHAPE_EINVAL as for the other calls; an empty batch is a no-op."""
+    L = shape.lib
+    out = C.c_void_p(0x3000)
+    o = shape.default_opts()
+    c = shape.queue_cfg()
+    assert shape.STATIC_MAX_STAMPS == 65536
+    big = _batch(shape, n=shape.STATIC_MAX_STAMPS + 1, n_pixels=(shape.STATIC_MAX_STAMPS + 1) * 256)
+    args = (None, out, out, out, None, out, out, None, None)
+    assert L.shape_fit_queue_static(C.byref(big), C.byref(o), C.byref(c), *args) == shape.ENOMEM
+    b = _batch(shape)
+    assert L.shape_fit_queue_static(None, C.byref(o), C.byref(c), *args) == shape.EINVAL
+    assert L.shape_fit_queue_static(C.byref(b), C.byref(o), None, *args) == shape.EINVAL
+    assert L.shape_fit_queue_static(C.byref(b), C.byref(o), C.byref(c),
+                                    None, None, out, out, None, out, out, None, None) == shape.EINVAL
+    e = _batch(shape, n=0, pixels=None, sigma=None)
+    assert L.shape_fit_queue_static(C.byref(e), C.byref(o), C.byref(c), *args) == shape.OK
+
+
 def test_star_moments_argument_errors(shape):
     L = shape.lib
     out = C.c_void_p(0x3000)

@@ -367,8 +367,9 @@ def bench_uneven(args):
     rec0, _, _ = shape.centroid(db, opts)
     rec1, _, _ = shape.moments(db, rec0, opts)
     t = time.time()
-    cfg, timings = autotune.tune_queue(db, rec1, opts, use_cache=False)
-    log("autotune %.1f s: %s" % (time.time() - t, [(d["cfg"], round(d["ms"], 2)) for d in timings]))
+    tuned = autotune.tune_queue(db, rec1, opts, use_cache=False)
+    cfg, drain_at = tuned["cfg"], int(tuned["drain_frac"] * db.n)
+    log("autotune %.1f s: best %s drain %.2f" % (time.time() - t, dict(team=cfg.team, team_min_side=cfg.team_min_side, grid=cfg.grid), tuned["drain_frac"]))
 
     def step(form, ev=None):
         r0, _, _ = shape.centroid(db, opts)
@@ -376,7 +377,8 @@ def bench_uneven(args):
         if ev:
             ev[0].record()
         if form == "queue":
-            fit = shape.fit_queue(db, rec=r1, opts=opts, cfg=cfg, use_graph=True)
+            fit = shape.fit_queue(db, rec=r1, opts=opts, cfg=cfg, use_graph=True,
+                                  drain_at=drain_at)
         else:
             fit = shape.fit_sersic(db, rec=r1, opts=opts)
         if ev:

@@ -243,22 +243,26 @@ int shape_star_moments(const shape_batch* batch, int32_t profile, const float* r
                        void* stream);
 
 /* ------------------------------------------------------------------------
- * Work-queue form of shape_fit_sersic for batches of uneven stamps (any mix
- * of sides and of Sersic / Moffat stamps).  The same LM trials as the fused
- * fit, one trial per stamp per step:
- *   shape_queue_start   orders the stamps largest side first (on the device)
- *                       and computes every stamp's starting point;
- *   shape_queue_step    one persistent launch: workgroups pop stamps from an
- *                       atomic cursor and advance each still-active stamp by
- *                       one LM trial (the state lives in the workspace);
+ * Work-queue form of shape_fit_sersic for large batches, uneven stamps (any
+ * mix of sides and of Sersic / Moffat stamps) and callers that drive the LM
+ * iteration themselves.  The same LM trials as the fused fit, with the same
+ * results bit for bit, split into batched passes:
+ *   shape_queue_start   orders the stamps largest side first (on the device),
+ *                       forms every stamp's starting point and runs the
+ *                       start sweeps (amplitudes, then the first full sweep);
+ *   shape_queue_step    one LM trial of every still-active stamp: a persistent
+ *                       sweep pass (waves pop stamps from atomic cursors and
+ *                       render model, Jacobian, chi^2, J^T r, J^T J) and a
+ *                       decide pass with one lane per stamp (amplitudes,
+ *                       accept / reject, damped FP64 solve, next trial);
+ *                       only the active stamps are visited;
  *   shape_queue_finish  writes the same outputs as shape_fit_sersic.
  * A step can be captured once into a hipGraph and replayed
  * (shape_queue_graph_*).  The caller owns the workspace (device memory of
  * shape_queue_workspace_bytes(n) bytes); the uint32 at byte offset 8,
  * `active`, counts the stamps still iterating after the last step and is
- * valid once the stream has synchronised.  A step is one persistent launch
- * per model present (Sersic, and Moffat when the batch has a model array).
- * Steps on one workspace must not overlap.
+ * valid once the stream has synchronised.  max_iter_lm steps finish every
+ * stamp.  Steps on one workspace must not overlap.
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t team;           /* waves per stamp for stamps with side >= team_min_side: 1, 2, 4 */
@@ -270,7 +274,7 @@ typedef struct {
 
 /* Defaults: team 1 (one wave per stamp), grid 0. */
 int shape_queue_default_cfg(shape_queue_cfg* cfg);
-/* Workspace bytes for n stamps (about 450 B per stamp). */
+/* Workspace bytes for n stamps (about 1.05 KB per stamp). */
 int shape_queue_workspace_bytes(int64_t n, size_t* bytes);
 /* Starting points (p_init [n][8] or, if NULL, the moments records rec [n][9]). */
 int shape_queue_start(const shape_batch* batch, const shape_opts* opts, const shape_queue_cfg* cfg,
@@ -279,6 +283,13 @@ int shape_queue_start(const shape_batch* batch, const shape_opts* opts, const sh
 /* One LM trial for every still-active stamp. */
 int shape_queue_step(const shape_batch* batch, const shape_opts* opts, const shape_queue_cfg* cfg,
                      void* ws, size_t ws_bytes, void* stream);
+/* Every still-active stamp finished in one persistent launch per model, one
+ * wave per stamp: its pending trial, then LM trials until it converges,
+ * stalls or reaches max_iter_lm (the results equal those of further steps).
+ * For the end of a fit, when few stamps remain and a step would cost more
+ * in launch and straggler time than in work.  Afterwards active = 0. */
+int shape_queue_drain(const shape_batch* batch, const shape_opts* opts, const shape_queue_cfg* cfg,
+                      void* ws, size_t ws_bytes, void* stream);
 /* Outputs, as shape_fit_sersic (stamps still active are flagged MAX_ITER). */
 int shape_queue_finish(const shape_batch* batch, const shape_opts* opts, void* ws,
                        size_t ws_bytes, float* p_out, float* chi2, float* perr, int32_t* iters,
@@ -299,9 +310,9 @@ int shape_queue_graph_destroy(shape_queue_graph* graph);
  * allocate device memory (code under hipGraph/stream capture, tight serving
  * loops, harnesses that forbid hipMalloc).  Same inputs and outputs as
  * shape_fit_sersic plus the queue configuration; it runs shape_queue_start,
- * max_iter_lm steps (a step skips the stamps that are done) and
+ * max_iter_lm steps (a step finds no work once every stamp is done) and
  * shape_queue_finish, with the workspace in a static device array of the
- * library (queue workspace of SHAPE_STATIC_MAX_STAMPS stamps, about 29 MB,
+ * library (queue workspace of SHAPE_STATIC_MAX_STAMPS stamps, about 69 MB,
  * held on every device the library runs on until the process ends).  The
  * results equal those of the three calls with a caller's workspace.
  *   n > SHAPE_STATIC_MAX_STAMPS returns SHAPE_ENOMEM before any work.

@@ -138,13 +138,15 @@ def _load():
     lib.shape_queue_start.argtypes = [bp, op, qp, vp, vp, vp, C.c_size_t, vp]
     lib.shape_queue_step.argtypes = [bp, op, qp, vp, C.c_size_t, vp]
     lib.shape_queue_finish.argtypes = [bp, op, vp, C.c_size_t, vp, vp, vp, vp, vp, vp, vp]
+    lib.shape_queue_drain.argtypes = [bp, op, qp, vp, C.c_size_t, vp]
     lib.shape_queue_graph_create.argtypes = [bp, op, qp, vp, C.c_size_t, C.POINTER(C.c_void_p)]
     lib.shape_queue_graph_launch.argtypes = [vp, vp]
     lib.shape_queue_graph_destroy.argtypes = [vp]
     lib.shape_fit_queue_static.argtypes = [bp, op, qp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     for f in ("shape_queue_default_cfg", "shape_queue_workspace_bytes", "shape_queue_start",
               "shape_queue_step", "shape_queue_finish", "shape_queue_graph_create",
-              "shape_queue_graph_launch", "shape_queue_graph_destroy", "shape_fit_queue_static"):
+              "shape_queue_graph_launch", "shape_queue_graph_destroy", "shape_fit_queue_static",
+              "shape_queue_drain"):
         getattr(lib, f).restype = C.c_int
     return lib
 
@@ -524,11 +526,14 @@ def queue_active(ws: torch.Tensor) -> int:
 
 def fit_queue(batch: DeviceBatch, rec: torch.Tensor | None = None,
               p_init: torch.Tensor | None = None, opts: ShapeOpts | None = None,
-              cfg: QueueCfg | None = None, use_graph: bool = True, check_every: int = 4,
-              want_perr: bool = False):
+              cfg: QueueCfg | None = None, use_graph: bool = True, check_every: int = 2,
+              want_perr: bool = False, drain_at: int = 4096):
     """Work-queue fit: shape_queue_start, then one LM trial per step (a hipGraph
     replay when use_graph) until every stamp is done or max_iter_lm steps, then
-    shape_queue_finish.  Returns the fit_sersic outputs plus the step count."""
+    shape_queue_finish.  The active count is read every check_every steps;
+    once it is at most drain_at (0: never) the remaining stamps are finished
+    by shape_queue_drain.  Returns the fit_sersic outputs plus the step count
+    and whether the drain ran."""
     opts = opts or default_opts()
     cfg = cfg or queue_cfg()
     n, dev = batch.n, batch.device
@@ -546,6 +551,7 @@ def fit_queue(batch: DeviceBatch, rec: torch.Tensor | None = None,
                                  _ptr(ws), nbytes, _stream(dev)), "shape_queue_start")
     graph = QueueGraph(batch, opts, cfg, ws) if use_graph else None
     steps = 0
+    drained = False
     try:
         while steps < opts.max_iter_lm:
             if graph:
@@ -554,15 +560,24 @@ def fit_queue(batch: DeviceBatch, rec: torch.Tensor | None = None,
                 _check(lib.shape_queue_step(C.byref(b), C.byref(opts), C.byref(cfg), _ptr(ws),
                                             nbytes, _stream(dev)), "shape_queue_step")
             steps += 1
-            if check_every and steps % check_every == 0 and queue_active(ws) == 0:
-                break
+            if check_every and steps % check_every == 0:
+                active = queue_active(ws)
+                if active == 0:
+                    break
+                if active <= drain_at:
+                    _check(lib.shape_queue_drain(C.byref(b), C.byref(opts), C.byref(cfg),
+                                                 _ptr(ws), nbytes, _stream(dev)),
+                           "shape_queue_drain")
+                    drained = True
+                    break
     finally:
         if graph:
             graph.close()
     _check(lib.shape_queue_finish(C.byref(b), C.byref(opts), _ptr(ws), nbytes, _ptr(p),
                                   _ptr(chi2), _ptr(perr), _ptr(it), _ptr(st), _ptr(sw),
                                   _stream(dev)), "shape_queue_finish")
-    return dict(p=p, chi2=chi2, perr=perr, iters=it, status=st, sweeps=sw, steps=steps)
+    return dict(p=p, chi2=chi2, perr=perr, iters=it, status=st, sweeps=sw, steps=steps,
+                drained=drained)
 
 
 def fit_queue_static(batch: DeviceBatch, rec: torch.Tensor | None = None,

@@ -1,30 +1,41 @@
-"""Autotuner for the work-queue fit: waves per stamp and the team threshold.
+"""Autotuner for the work-queue fit: waves per stamp, team threshold,
+persistent grid and the point where the drain pass takes over.
 
-For a batch of uneven stamps it times a few queue steps for each candidate
-configuration (team of 1, 2 or 4 waves for stamps at or above a threshold
-side; persistent grid sized by the device or doubled) on an evenly spaced
-sample of the batch, keeps the fastest, and caches the choice in a JSON file
-keyed by the device, the free mask, the storage type and a coarse histogram of
-the stamp sides.  The cache lives in $SHAPE_TUNE_CACHE (default
-~/.cache/shape/queue_tune.json).
+For a batch it times the whole queue fit (start, graph-replayed steps, drain,
+finish) for each candidate on an evenly spaced sample of the batch: teams of
+1, 2 or 4 waves for stamps at or above a threshold side; the persistent grid
+at the resident workgroup count or half of it; the drain once the active
+stamps fall to 2%, 8% or 25% of the batch.  It keeps the fastest and caches
+the choice in a JSON file keyed by the device, the free mask, the storage
+type and a coarse histogram of the stamp sides.  The cache lives in
+$SHAPE_TUNE_CACHE (default ~/.cache/shape/queue_tune.json).
 """
 from __future__ import annotations
 
+import itertools
 import json
 import os
 
 import torch
 
-from . import (DeviceBatch, default_opts, lib, queue_cfg, queue_workspace_bytes, _check, _ptr,
-               _stream)
+from . import DeviceBatch, default_opts, fit_queue, queue_cfg
 
-CANDIDATES = [
-    dict(team=1, team_min_side=96, grid=0),
-    dict(team=2, team_min_side=64, grid=0),
-    dict(team=2, team_min_side=96, grid=0),
-    dict(team=4, team_min_side=96, grid=0),
-    dict(team=4, team_min_side=112, grid=0),
-]
+TEAMS = [dict(team=1, team_min_side=96), dict(team=2, team_min_side=64),
+         dict(team=2, team_min_side=96), dict(team=4, team_min_side=96)]
+GRID_FRACTIONS = [1.0, 0.5]        # of the resident single-wave workgroups
+DRAIN_FRACTIONS = [0.02, 0.08, 0.25]
+
+
+def candidates(device, free_mask=0xFF):
+    """Every configuration tried: (queue_cfg fields, drain fraction)."""
+    cus = torch.cuda.get_device_properties(device).multi_processor_count
+    out = []
+    for t, g, d in itertools.product(TEAMS, GRID_FRACTIONS, DRAIN_FRACTIONS):
+        if free_mask != 0xFF and t["team"] != 1:
+            continue
+        grid = 0 if g == 1.0 else int(cus * 16 * g / t["team"])
+        out.append((dict(t, grid=grid), d))
+    return out
 
 
 def _cache_path():
@@ -58,20 +69,12 @@ def _subset(batch: DeviceBatch, max_stamps: int) -> DeviceBatch:
                        model=None if batch.model is None else batch.model[idx].contiguous())
 
 
-def time_queue(batch: DeviceBatch, rec: torch.Tensor, opts, cfg, steps: int = 3) -> float:
-    """Milliseconds for queue start + `steps` steps with configuration cfg."""
-    import ctypes as C
-    n, dev = batch.n, batch.device
-    nbytes = queue_workspace_bytes(n)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    b = batch.c_struct()
+def time_queue(batch: DeviceBatch, rec: torch.Tensor, opts, cfg, drain_frac: float) -> float:
+    """Milliseconds for the whole queue fit of batch with configuration cfg."""
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    _check(lib.shape_queue_start(C.byref(b), C.byref(opts), C.byref(cfg), None, _ptr(rec),
-                                 _ptr(ws), nbytes, _stream(dev)), "shape_queue_start")
-    for _ in range(steps):
-        _check(lib.shape_queue_step(C.byref(b), C.byref(opts), C.byref(cfg), _ptr(ws), nbytes,
-                                    _stream(dev)), "shape_queue_step")
+    fit_queue(batch, rec=rec, opts=opts, cfg=cfg, use_graph=True,
+              drain_at=int(drain_frac * batch.n))
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1)
@@ -79,7 +82,8 @@ def time_queue(batch: DeviceBatch, rec: torch.Tensor, opts, cfg, steps: int = 3)
 
 def tune_queue(batch: DeviceBatch, rec: torch.Tensor, opts=None, sample: int = 65536,
                use_cache: bool = True, verbose: bool = False):
-    """Return the fastest queue_cfg for this batch (and the timings tried)."""
+    """The fastest configuration for this batch: dict(cfg=queue_cfg, drain_frac,
+    timings=[dict(cfg, drain_frac, ms), ...])."""
     opts = opts or default_opts()
     key = _signature(batch, opts)
     path = _cache_path()
@@ -89,31 +93,31 @@ def tune_queue(batch: DeviceBatch, rec: torch.Tensor, opts=None, sample: int = 6
             cache = json.load(open(path))
         except (OSError, ValueError):
             cache = {}
-        if key in cache:
-            return queue_cfg(**cache[key]["cfg"]), cache[key]["timings"]
+        if key in cache and "drain_frac" in cache[key]:
+            e = cache[key]
+            return dict(cfg=queue_cfg(**e["cfg"]), drain_frac=e["drain_frac"], timings=e["timings"])
     sub = _subset(batch, sample)
     sub_rec = rec
     if sub is not batch:
         idx = torch.linspace(0, batch.n - 1, sub.n, device=batch.device).long()
         sub_rec = rec[idx].contiguous()
-    cands = [c for c in CANDIDATES if opts.free_mask == 0xFF or c["team"] == 1]
     timings = []
-    for c in cands:
+    for c, d in candidates(batch.device, opts.free_mask):
         cfg = queue_cfg(**c)
-        time_queue(sub, sub_rec, opts, cfg, steps=1)           # warm-up
-        ms = min(time_queue(sub, sub_rec, opts, cfg) for _ in range(2))
-        timings.append(dict(cfg=c, ms=ms))
+        time_queue(sub, sub_rec, opts, cfg, d)           # warm-up
+        ms = min(time_queue(sub, sub_rec, opts, cfg, d) for _ in range(2))
+        timings.append(dict(cfg=c, drain_frac=d, ms=ms))
         if verbose:
-            print("autotune", c, "%.3f ms" % ms, flush=True)
+            print("autotune", c, d, "%.3f ms" % ms, flush=True)
     best = min(timings, key=lambda t: t["ms"])
     if use_cache:
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
-            cache[key] = dict(cfg=best["cfg"], timings=timings)
+            cache[key] = dict(cfg=best["cfg"], drain_frac=best["drain_frac"], timings=timings)
             tmp = path + ".tmp%d" % os.getpid()
             with open(tmp, "w") as f:
                 json.dump(cache, f, indent=1)
             os.replace(tmp, path)
         except OSError:
             pass
-    return queue_cfg(**best["cfg"]), timings
+    return dict(cfg=queue_cfg(**best["cfg"]), drain_frac=best["drain_frac"], timings=timings)

@@ -251,6 +251,13 @@ int shape_queue_step(const shape_batch* b, const shape_opts* o, const shape_queu
   return from_hip(launch_queue_step(*b, kopts(o), ws, qcfg(c), (hipStream_t)stream));
 }
 
+int shape_queue_drain(const shape_batch* b, const shape_opts* o, const shape_queue_cfg* c, void* ws,
+                      size_t ws_bytes, void* stream) {
+  int rc = check_queue(b, o, c, ws, ws_bytes);
+  if (rc != SHAPE_OK || b->n == 0) return rc;
+  return from_hip(launch_queue_drain(*b, kopts(o), ws, qcfg(c), (hipStream_t)stream));
+}
+
 int shape_queue_finish(const shape_batch* b, const shape_opts* o, void* ws, size_t ws_bytes,
                        float* p_out, float* chi2, float* perr, int32_t* iters, uint32_t* status,
                        int32_t* sweeps, void* stream) {

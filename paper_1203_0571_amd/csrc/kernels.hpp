@@ -23,21 +23,30 @@ struct QCfg {
 };
 
 // Workspace layout of the queue form: a 256-byte header, the cursor lines,
-// the (model, side) histogram, the stamp order and one state row per stamp.
+// the (model, side) histogram, the stamp order, two stamp lists and the
+// per-stamp state (parameters, trial point, current sums, damping, counters,
+// phase, the last sweep's sums and the pending sweep's constants), each an
+// array over the stamps.
 constexpr int kBuckets = 512;
+constexpr int kClasses = 4;        // (Sersic, Moffat) x (team of waves, single wave)
 constexpr int kCursors = 8;
 constexpr int kCursorStride = 32;  // uint32 per cursor line (128 bytes)
-constexpr size_t kCursorBytes = 2 * 2 * kCursors * kCursorStride * 4;
-constexpr size_t kQueueStateBytes = 448;
+constexpr size_t kCursorBytes = (size_t)kClasses * kCursors * kCursorStride * 4;
+constexpr int kConstRow = 32;      // floats of sweep constants per stamp (27 used)
 __host__ __device__ constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 __host__ __device__ constexpr size_t queue_workspace_bytes(int64_t n) {
-  return 256 + kCursorBytes + align256(kBuckets * 4) + align256((size_t)n * 4) +
-         (size_t)n * kQueueStateBytes;
+  const size_t m = (size_t)n;
+  return 256 + kCursorBytes + align256(kBuckets * 4) + 3 * align256(m * 4) +  // order, lists
+         2 * align256(m * 64) + align256(m * 45 * 8) +                        // p, pt, sums
+         2 * align256(m * 8) + 4 * align256(m * 4) +                          // lambda, smax, ints
+         align256(m * 45 * 8) + align256(m * kConstRow * 4);
 }
 hipError_t launch_queue_start(const shape_batch& b, const KOpts& o, void* ws, const float* p_init,
                               const float* rec, const QCfg& cfg, hipStream_t stream);
 hipError_t launch_queue_step(const shape_batch& b, const KOpts& o, void* ws, const QCfg& cfg,
                              hipStream_t stream);
+hipError_t launch_queue_drain(const shape_batch& b, const KOpts& o, void* ws, const QCfg& cfg,
+                              hipStream_t stream);
 hipError_t launch_queue_finish(const shape_batch& b, const KOpts& o, void* ws, float* p_out,
                                float* chi2, float* perr, int32_t* iters, uint32_t* status,
                                int32_t* sweeps, hipStream_t stream);

@@ -103,6 +103,36 @@ __device__ __forceinline__ bool gj_solve(double (&a)[N], double (&b)[M], int lan
   return ok;
 }
 
+// The same elimination as gj_solve within one lane (a[r] = row r): every
+// value is formed by the same operations in the same order, so the result is
+// bit-identical to the cross-lane form.  Used where one lane owns a stamp.
+template <int N>
+__device__ __forceinline__ bool gj_serial(double (&a)[N][N], double (&b)[N]) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const double piv = a[j][j];
+    ok = ok && piv > 0.0;
+    const double ip = rcp_f64(piv);
+    double pr[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) pr[c] = a[j][c] * ip;
+    const double pb = b[j] * ip;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      if (r == j) continue;
+      const double f = a[r][j];
+#pragma unroll
+      for (int c = 0; c < N; ++c) a[r][c] = fma(-f, pr[c], a[r][c]);
+      b[r] = fma(-f, pb, b[r]);
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c) a[j][c] = pr[c];
+    b[j] = pb;
+  }
+  return ok;
+}
+
 // Synchronise a team of TEAM waves (a lone wave needs no barrier).
 template <int TEAM>
 __device__ __forceinline__ void team_sync() {
@@ -112,42 +142,52 @@ __device__ __forceinline__ void team_sync() {
     __syncthreads();
 }
 
-// One sweep at trial t; the team's reduced sums are left in S (LDS, kSums
-// doubles).  xs is LDS scratch of TEAM * kSums doubles for the cross-wave
-// combination (unused for TEAM == 1).  tid = thread index within the team.
+// One sweep at trial t; the team's reduced sums are left in S (kSums doubles,
+// entry k at S[k * stride]: LDS for the fused fit, the stamp's column of the
+// workspace for the batched form).  xs is LDS scratch of TEAM * kSums doubles
+// for the cross-wave combination (unused for TEAM == 1).  tid = thread index
+// within the team; stage: the LDS buffer of kLayoutStaged (kStageBytes).
 template <int DT, int MODEL, uint32_t EM, int TEAM, int LAYOUT = kLayoutAny>
 __device__ __forceinline__ void sweep_sums(const shape_batch& b, const Stamp& st, const TrialF& t,
-                                  double* S, double* xs, int tid) {
+                                           double* S, double* xs, int tid, int64_t stride = 1,
+                                           void* stage = nullptr) {
   Acc<EM> acc;
-  sweep<DT, MODEL, EM, kWave * TEAM, float, LAYOUT>(b, st, t, acc, tid);
+  sweep<DT, MODEL, EM, kWave * TEAM, float, LAYOUT>(b, st, t, acc, tid, stage);
   const int lane = tid & (kWave - 1);
-  double* dst = (TEAM == 1) ? S : xs + (tid / kWave) * kSums;
   team_sync<TEAM>();  // previous readers of S / xs are done
-  reduce_store<EM>(acc, dst, lane);
+  if constexpr (TEAM == 1) {
+    reduce_store<EM>(acc, S, lane, stride);
+  } else {
+    reduce_store<EM>(acc, xs + (tid / kWave) * kSums, lane);
+  }
   team_sync<TEAM>();
   if constexpr (TEAM > 1) {
     if (tid < kSums) {
       double v = xs[tid];
 #pragma unroll
       for (int w = 1; w < TEAM; ++w) v += xs[w * kSums + tid];
-      S[tid] = v;
+      S[tid * stride] = v;
     }
     team_sync<TEAM>();
   }
-  if (tid == 0) S[sa(7, 7)] = (double)st.npix;
+  if (tid == 0) S[sa(7, 7) * stride] = (double)st.npix;
   team_sync<TEAM>();
 }
 
-// Solve the free amplitudes (LIN: bit 6 = I0, bit 7 = sky) from sums taken at
-// amplitudes (I0, sky) and move the sums to that optimum (thread 0 rewrites S).
-// Returns false when the amplitude block is singular; otherwise (d6, d7) are
-// the amplitude changes.
+// Per-stamp arithmetic of one LM trial, lane-local: the fused kernel runs it
+// on one thread of the team (on the sums in LDS), the batched form on one lane
+// per stamp; both call these same routines, so both forms compute the same
+// values.
+
+// The free amplitudes (LIN: bit 6 = I0, bit 7 = sky) from sums S taken at
+// amplitudes (I0, sky): ok = false when the amplitude block is singular,
+// otherwise (d6, d7) are the amplitude changes.
 struct AmpStep {
   bool ok;
   double d6, d7;
 };
-template <uint32_t EM, uint32_t LIN, int TEAM>
-__device__ __forceinline__ AmpStep profile_amplitudes(double* S, double I0, int tid) {
+template <uint32_t LIN>
+__device__ __forceinline__ AmpStep amp_solve(const double* S) {
   AmpStep r{true, 0.0, 0.0};
   const double g6 = S[sg(6)], g7 = S[sg(7)];
   if constexpr (has(LIN, 6) && has(LIN, 7)) {
@@ -163,38 +203,68 @@ __device__ __forceinline__ AmpStep profile_amplitudes(double* S, double I0, int 
   } else if constexpr (has(LIN, 7)) {
     r.d7 = g7 / S[sa(7, 7)];
   }
+  return r;
+}
+
+// Move the sums S (taken at amplitude I0 > 0) to the amplitude optimum r, in
+// place (A_NL and g_N still hold the old values while they are read).
+template <uint32_t EM, uint32_t LIN>
+__device__ __forceinline__ void amp_apply(double* S, const AmpStep& r, double I0) {
+  const double g6 = S[sg(6)], g7 = S[sg(7)];
   const double d6 = r.d6, d7 = r.d7;
-  const double sc = (I0 + d6) * rcp_f64(I0);   // I0 > 0 at every evaluated point
-  team_sync<TEAM>();
-  if (tid == 0) {  // in place: A_NL and g_N still hold the old values here
-    S[0] -= g6 * d6 + g7 * d7;
+  const double sc = (I0 + d6) * rcp_f64(I0);
+  S[0] -= g6 * d6 + g7 * d7;
 #pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      if (!has(EM, a)) continue;
-      const double a6 = S[sa(a, 6)], a7 = S[sa(a, 7)];
-      S[sg(a)] = sc * (S[sg(a)] - a6 * d6 - a7 * d7);
+  for (int a = 0; a < 6; ++a) {
+    if (!has(EM, a)) continue;
+    const double a6 = S[sa(a, 6)], a7 = S[sa(a, 7)];
+    S[sg(a)] = sc * (S[sg(a)] - a6 * d6 - a7 * d7);
 #pragma unroll
-      for (int c = a; c < 6; ++c)
-        if (has(EM, c)) S[sa(a, c)] *= sc * sc;
-      S[sa(a, 6)] = a6 * sc;
-      S[sa(a, 7)] = a7 * sc;
-    }
-    if constexpr (has(LIN, 6)) S[sg(6)] = 0.0;
-    if constexpr (has(LIN, 7)) S[sg(7)] = 0.0;
+    for (int c = a; c < 6; ++c)
+      if (has(EM, c)) S[sa(a, c)] *= sc * sc;
+    S[sa(a, 6)] = a6 * sc;
+    S[sa(a, 7)] = a7 * sc;
   }
+  if constexpr (has(LIN, 6)) S[sg(6)] = 0.0;
+  if constexpr (has(LIN, 7)) S[sg(7)] = 0.0;
+}
+
+// The team form: every thread solves, thread 0 rewrites S (in LDS).
+template <uint32_t EM, uint32_t LIN, int TEAM>
+__device__ __forceinline__ AmpStep profile_amplitudes(double* S, double I0, int tid) {
+  const AmpStep r = amp_solve<LIN>(S);
+  if (!r.ok) return r;
+  team_sync<TEAM>();
+  if (tid == 0) amp_apply<EM, LIN>(S, r, I0);
   team_sync<TEAM>();
   return r;
 }
 
-// Starting point: p from p_init or the moments record, the amplitude optimum
-// at that shape (Sec. 4.1) and the first sweep, whose profiled sums become the
-// current point (W.sums[W.cur]).  The state ends in W.L.
-template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT = kLayoutAny>
-__device__ __forceinline__ void lm_start(const shape_batch& b, const KOpts& o, const Stamp& st,
-                                         const float* p_init, const float* rec, int64_t s,
-                                         LmShared& W, double* xs, int tid) {
-  constexpr uint32_t EM = eff_mask(MASK, MODEL);
-  constexpr uint32_t LIN = EM & 0xC0u;
+// Entry (ka, kc) of the Schur complement of the amplitude block (undamped):
+//   M_ac = A_ac - A_aL (A_LL)^-1 A_Lc = A_ac - u_a A_c6 - w_a A_c7.
+template <uint32_t LIN>
+__device__ __forceinline__ double schur_entry(const double* C, int ka, int kc) {
+  double v = C[sa(ka, kc)];
+  if constexpr (has(LIN, 6) && has(LIN, 7)) {
+    const double L00 = C[sa(6, 6)], L01 = C[sa(6, 7)], L11 = C[sa(7, 7)];
+    const double idet = rcp_f64(L00 * L11 - L01 * L01);   // (not positive: the solve fails)
+    const double a6 = C[sa(ka, 6)], a7 = C[sa(ka, 7)];
+    const double u = (L11 * a6 - L01 * a7) * idet, w = (L00 * a7 - L01 * a6) * idet;
+    v -= u * C[sa(kc, 6)] + w * C[sa(kc, 7)];
+  } else if constexpr (has(LIN, 6)) {
+    v -= C[sa(ka, 6)] * C[sa(kc, 6)] / C[sa(6, 6)];
+  } else if constexpr (has(LIN, 7)) {
+    v -= C[sa(ka, 7)] * C[sa(kc, 7)] / C[sa(7, 7)];
+  }
+  return v;
+}
+
+// The starting point: p from p_init or the moments record (x0, y0, e1, e2 of
+// the moments; Re = the record's size, or r50 where it is undefined; Moffat
+// rd from r50 and beta; n = n0; I0 = 1, sky = sky0), and the fresh state.
+template <int MODEL>
+__device__ __forceinline__ LmState start_point(const KOpts& o, const Stamp& st, const float* p_init,
+                                               const float* rec, int64_t s) {
   LmState L;
   double* p = L.p;
   if (p_init) {
@@ -232,6 +302,149 @@ __device__ __forceinline__ void lm_start(const shape_batch& b, const KOpts& o, c
     L.stt = SHAPE_ST_BAD_INPUT;
     L.done = 1;
   }
+  return L;
+}
+
+// What a trial's decision needs of the current point's sums C besides the
+// damped system: the right-hand side g_N of the step and the amplitude block.
+template <int NN>
+struct StepRhs {
+  double g[NN];
+  double l66, l67, l77;
+};
+template <uint32_t NL, int NN>
+__device__ __forceinline__ StepRhs<NN> step_rhs(const double* C) {
+  StepRhs<NN> r;
+#pragma unroll
+  for (int a = 0; a < NN; ++a) r.g[a] = C[sg(nth_bit(NL, a))];
+  r.l66 = C[sa(6, 6)];
+  r.l67 = C[sa(6, 7)];
+  r.l77 = C[sa(7, 7)];
+  return r;
+}
+
+// After the solve of the damped step x (solved: the elimination succeeded):
+// counts the trial, forms the trial point pt and decides.  Returns the step's
+// max_k |x_k| / s_k when the trial needs a sweep, -1 when it does not (the
+// fit converged on a small Gauss-Newton step, or the trial left the box and is
+// rejected).  R holds the current point's right-hand side and amplitude block.
+template <int MODEL, uint32_t NL, uint32_t LIN, int NN>
+__device__ __forceinline__ double lm_propose(LmState& L, const StepRhs<NN>& R,
+                                             const double (&x)[NN], bool solved, const KOpts& o,
+                                             const Stamp& st, double* ptout) {
+  bool ok = solved;
+  if constexpr (has(LIN, 6) && has(LIN, 7))
+    ok = ok && R.l66 * R.l77 - R.l67 * R.l67 > 0.0;
+  else if constexpr (has(LIN, 6))
+    ok = ok && R.l66 > 0.0;
+  else if constexpr (has(LIN, 7))
+    ok = ok && R.l77 > 0.0;
+  ++L.it;
+  bool inside = false;
+  double smax = 0.0, q = 0.0;   // q = d^T A_lambda d = d^T g
+#pragma unroll
+  for (int k = 0; k < 8; ++k) ptout[k] = L.p[k];
+  if (!ok) {
+    L.stt |= SHAPE_ST_SINGULAR;
+  } else {
+    double pt[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) pt[k] = L.p[k];
+    // (the scales only feed the stopping test: FP32 reciprocals)
+    const double iscl[8] = {1.0, 1.0, 1.0, 1.0, (double)fast_rcp((float)L.p[4]),
+                            (double)fast_rcp((float)L.p[5]), (double)fast_rcp(fabsf((float)L.p[6])),
+                            (double)fast_rcp((float)st.sigma)};
+#pragma unroll
+    for (int a = 0; a < NN; ++a) {
+      pt[nth_bit(NL, a)] += x[a];
+      smax = fmax(smax, fabs(x[a]) * iscl[nth_bit(NL, a)]);
+      q += x[a] * R.g[a];
+    }
+    const double gmax2 = o.gmax * o.gmax;
+    inside = pt[2] * pt[2] + pt[3] * pt[3] < gmax2 && pt[4] >= 0.1 &&
+             pt[4] <= (double)st.side && pt[6] > 0.0 && __builtin_isfinite(pt[0]) &&
+             __builtin_isfinite(pt[1]) && __builtin_isfinite(pt[7]);
+    if (MODEL == SHAPE_SERSIC) inside = inside && pt[5] >= 0.2 && pt[5] <= 10.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ptout[k] = pt[k];
+  }
+  // At small damping the step is the Gauss-Newton step from the current
+  // point; when it is already below the tolerances (max_k |d_k| / s_k <
+  // tol_lm, or d^T A_lambda d = d^T g below tol_sigma^2 sigma^2: d^T A d /
+  // sigma^2 bounds (d_k / sigma_k)^2 for every k and A_lambda >= A, so every
+  // parameter would move by less than tol_sigma standard errors) the current
+  // point is the result and the trial needs no sweep.
+  const double sig2 = st.sigma * st.sigma;
+  const bool small_step = inside && L.lambda <= 1e-3 &&
+                          (smax < o.tol_lm || q < o.tol_sigma * o.tol_sigma * sig2);
+  if (small_step) {
+    L.stt |= SHAPE_ST_CONVERGED;
+    L.done = 1;
+    return -1.0;  // no sweep for this trial
+  }
+  if (!inside) {  // rejected before any sweep
+    L.lambda *= 10.0;
+    if (L.lambda > 1e10) {
+      L.stt |= SHAPE_ST_STALLED;
+      L.done = 1;
+    }
+    return -1.0;  // no sweep for this trial
+  }
+  ++L.nsweep;
+  return smax;
+}
+
+// The verdict on a swept trial: pt is the trial point with the amplitudes of
+// its sweep (a: their optimum at the trial shape, when LIN != 0), c2t the
+// trial's profiled chi^2 sum and c2c the current point's.  Accepts (L.p = pt,
+// less damping, converged on a step below tol_lm) or rejects (more damping,
+// stalled above 1e10).  Returns whether the trial was accepted.
+template <uint32_t LIN>
+__device__ __forceinline__ bool lm_judge(LmState& L, double* pt, const AmpStep& a, double smax,
+                                         double c2t, double c2c, const KOpts& o) {
+  bool inside = true;
+  if (LIN != 0u) {
+    pt[6] += a.d6;
+    pt[7] += a.d7;
+    inside = a.ok && pt[6] > 0.0 && __builtin_isfinite(pt[7]);
+  }
+  bool accepted = false;
+  if (!inside) {
+    L.lambda *= 10.0;
+    if (L.lambda > 1e10) {
+      L.stt |= SHAPE_ST_STALLED;
+      L.done = 1;
+    }
+  } else if (__builtin_isfinite(c2t) && c2t <= c2c * (1.0 + o.chi2_rtol)) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) L.p[k] = pt[k];
+    accepted = true;
+    L.lambda = fmax(L.lambda * 0.1, 1e-9);
+    if (smax < o.tol_lm) {   // a short step taken at larger damping
+      L.stt |= SHAPE_ST_CONVERGED;
+      L.done = 1;
+    }
+  } else {
+    L.lambda *= 10.0;
+    if (L.lambda > 1e10) {
+      L.stt |= SHAPE_ST_STALLED;
+      L.done = 1;
+    }
+  }
+  return accepted;
+}
+
+// Starting point: p from p_init or the moments record, the amplitude optimum
+// at that shape (Sec. 4.1) and the first sweep, whose profiled sums become the
+// current point (W.sums[W.cur]).  The state ends in W.L.
+template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT = kLayoutAny>
+__device__ __forceinline__ void lm_start(const shape_batch& b, const KOpts& o, const Stamp& st,
+                                         const float* p_init, const float* rec, int64_t s,
+                                         LmShared& W, double* xs, int tid) {
+  constexpr uint32_t EM = eff_mask(MASK, MODEL);
+  constexpr uint32_t LIN = EM & 0xC0u;
+  LmState L = start_point<MODEL>(o, st, p_init, rec, s);
+  double* p = L.p;
   if (tid == 0) W.cur = 0;
   double* C = W.sums[0];
   // Linear start: the free amplitudes' optimum at the starting shape, from one
@@ -270,6 +483,35 @@ __device__ __forceinline__ void lm_start(const shape_batch& b, const KOpts& o, c
   store_L<TEAM>(W, L, tid);
 }
 
+// The second half of a trial (W.smax >= 0): the sweep at the trial point W.pt
+// into the other sums buffer, the amplitudes at the trial shape, and the
+// verdict; an accepted trial's sums become current.
+template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT = kLayoutAny, bool PROF = true>
+__device__ __forceinline__ void lm_sweep_judge(const shape_batch& b, const KOpts& o,
+                                               const Stamp& st, LmShared& W, double* xs,
+                                               int tid) {
+  constexpr uint32_t EM = eff_mask(MASK, MODEL);
+  constexpr uint32_t LIN = PROF ? (EM & 0xC0u) : 0u;  // profiled amplitudes
+  const int cur = W.cur;
+  // the sweep at the trial point (nothing else is live here)
+  double* T = W.sums[cur ^ 1];
+  sweep_sums<DT, MODEL, EM, TEAM, LAYOUT>(b, st, make_trial(W.pt, MODEL, o.moffat_beta), T, xs, tid);
+  // amplitudes at the trial shape, then accept or reject
+  LmState L = load_L(W);
+  double pt[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) pt[k] = W.pt[k];
+  AmpStep a{true, 0.0, 0.0};
+  if (LIN != 0u) a = profile_amplitudes<EM, LIN, TEAM>(T, pt[6], tid);
+  const bool accepted = lm_judge<LIN>(L, pt, a, W.smax, T[0], W.sums[cur][0], o);
+  team_sync<TEAM>();
+  if (tid == 0) {
+    W.L = L;
+    W.cur = accepted ? cur ^ 1 : cur;
+  }
+  team_sync<TEAM>();
+}
+
 // One LM trial from the current sums; the trial's sums go to the other buffer
 // and become current when the trial is accepted.  Sets W.L.done when the fit
 // has converged or stalled; the caller enforces max_iter_lm.
@@ -296,19 +538,7 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
       c -= a + 1;
       ++a;
     }
-    const int ka = nth_bit(NL, a), kc = nth_bit(NL, c);
-    double v = C[sa(ka, kc)];
-    if constexpr (has(LIN, 6) && has(LIN, 7)) {
-      const double L00 = C[sa(6, 6)], L01 = C[sa(6, 7)], L11 = C[sa(7, 7)];
-      const double idet = rcp_f64(L00 * L11 - L01 * L01);   // (not positive: the solve fails)
-      const double a6 = C[sa(ka, 6)], a7 = C[sa(ka, 7)];
-      const double u = (L11 * a6 - L01 * a7) * idet, w = (L00 * a7 - L01 * a6) * idet;
-      v -= u * C[sa(kc, 6)] + w * C[sa(kc, 7)];
-    } else if constexpr (has(LIN, 6)) {
-      v -= C[sa(ka, 6)] * C[sa(kc, 6)] / C[sa(6, 6)];
-    } else if constexpr (has(LIN, 7)) {
-      v -= C[sa(ka, 7)] * C[sa(kc, 7)] / C[sa(7, 7)];
-    }
+    double v = schur_entry<LIN>(C, nth_bit(NL, a), nth_bit(NL, c));
     if (a == c) v *= 1.0 + W.L.lambda;
     W.M[tid] = v;
   }
@@ -336,118 +566,13 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
   for (int r = 0; r < NN; ++r) x[r] = read_lane(xr, r);
   if (tid == 0) {
     LmState L = W.L;
-    const double* C = W.sums[cur];
-    bool ok = solved;
-    if constexpr (has(LIN, 6) && has(LIN, 7))
-      ok = ok && C[sa(6, 6)] * C[sa(7, 7)] - C[sa(6, 7)] * C[sa(6, 7)] > 0.0;
-    else if constexpr (has(LIN, 6))
-      ok = ok && C[sa(6, 6)] > 0.0;
-    else if constexpr (has(LIN, 7))
-      ok = ok && C[sa(7, 7)] > 0.0;
-    ++L.it;
-    bool inside = false;
-    double smax = 0.0, q = 0.0;   // q = d^T A_lambda d = d^T g
-#pragma unroll
-    for (int k = 0; k < 8; ++k) W.pt[k] = L.p[k];
-    if (!ok) {
-      L.stt |= SHAPE_ST_SINGULAR;
-    } else {
-      double pt[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) pt[k] = L.p[k];
-      // (the scales only feed the stopping test: FP32 reciprocals)
-      const double iscl[8] = {1.0, 1.0, 1.0, 1.0, (double)fast_rcp((float)L.p[4]),
-                              (double)fast_rcp((float)L.p[5]), (double)fast_rcp(fabsf((float)L.p[6])),
-                              (double)fast_rcp((float)st.sigma)};
-#pragma unroll
-      for (int a = 0; a < NN; ++a) {
-        pt[nth_bit(NL, a)] += x[a];
-        smax = fmax(smax, fabs(x[a]) * iscl[nth_bit(NL, a)]);
-        q += x[a] * C[sg(nth_bit(NL, a))];
-      }
-      const double gmax2 = o.gmax * o.gmax;
-      inside = pt[2] * pt[2] + pt[3] * pt[3] < gmax2 && pt[4] >= 0.1 &&
-               pt[4] <= (double)st.side && pt[6] > 0.0 && __builtin_isfinite(pt[0]) &&
-               __builtin_isfinite(pt[1]) && __builtin_isfinite(pt[7]);
-      if (MODEL == SHAPE_SERSIC) inside = inside && pt[5] >= 0.2 && pt[5] <= 10.0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) W.pt[k] = pt[k];
-    }
-    // At small damping the step is the Gauss-Newton step from the current
-    // point; when it is already below the tolerances (max_k |d_k| / s_k <
-    // tol_lm, or d^T A_lambda d = d^T g below tol_sigma^2 sigma^2: d^T A d /
-    // sigma^2 bounds (d_k / sigma_k)^2 for every k and A_lambda >= A, so every
-    // parameter would move by less than tol_sigma standard errors) the current
-    // point is the result and the trial needs no sweep.
-    const double sig2 = st.sigma * st.sigma;
-    const bool small_step = inside && L.lambda <= 1e-3 &&
-                            (smax < o.tol_lm || q < o.tol_sigma * o.tol_sigma * sig2);
-    if (small_step) {
-      L.stt |= SHAPE_ST_CONVERGED;
-      L.done = 1;
-      W.smax = -1.0;  // no sweep for this trial
-    } else if (!inside) {  // rejected before any sweep
-      L.lambda *= 10.0;
-      if (L.lambda > 1e10) {
-        L.stt |= SHAPE_ST_STALLED;
-        L.done = 1;
-      }
-      W.smax = -1.0;  // no sweep for this trial
-    } else {
-      ++L.nsweep;
-      W.smax = smax;
-    }
+    W.smax = lm_propose<MODEL, NL, LIN, NN>(L, step_rhs<NL, NN>(W.sums[cur]), x, solved, o, st,
+                                            W.pt);
     W.L = L;
   }
   team_sync<TEAM>();
   if (W.smax < 0.0) return;
-  // Phase 2: the sweep at the trial point (nothing else is live here).
-  double* T = W.sums[cur ^ 1];
-  sweep_sums<DT, MODEL, EM, TEAM, LAYOUT>(b, st, make_trial(W.pt, MODEL, o.moffat_beta), T, xs, tid);
-  // Phase 3: amplitudes at the trial shape, then accept or reject.
-  LmState L = load_L(W);
-  double pt[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) pt[k] = W.pt[k];
-  const double smax = W.smax;
-  bool inside = true;
-  if (LIN != 0u) {
-    const AmpStep a = profile_amplitudes<EM, LIN, TEAM>(T, pt[6], tid);
-    pt[6] += a.d6;
-    pt[7] += a.d7;
-    inside = a.ok && pt[6] > 0.0 && __builtin_isfinite(pt[7]);
-  }
-  const double c2t = T[0];
-  const double c2c = W.sums[cur][0];
-  int next = cur;
-  if (!inside) {
-    L.lambda *= 10.0;
-    if (L.lambda > 1e10) {
-      L.stt |= SHAPE_ST_STALLED;
-      L.done = 1;
-    }
-  } else if (__builtin_isfinite(c2t) && c2t <= c2c * (1.0 + o.chi2_rtol)) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) L.p[k] = pt[k];
-    next = cur ^ 1;
-    L.lambda = fmax(L.lambda * 0.1, 1e-9);
-    if (smax < o.tol_lm) {   // a short step taken at larger damping
-      L.stt |= SHAPE_ST_CONVERGED;
-      L.done = 1;
-    }
-  } else {
-    L.lambda *= 10.0;
-    if (L.lambda > 1e10) {
-      L.stt |= SHAPE_ST_STALLED;
-      L.done = 1;
-    }
-  }
-  team_sync<TEAM>();
-  if (tid == 0) {
-    W.L = L;
-    W.cur = next;
-  }
-  team_sync<TEAM>();
+  lm_sweep_judge<DT, MODEL, MASK, TEAM, LAYOUT, PROF>(b, o, st, W, xs, tid);
 }
 
 // Whether the end point lies on the edge of the parameter box: a fitted

@@ -4,6 +4,8 @@
 // sum r^2, J^T r (FP64) and J^T J (FP32) over the stamp.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace shape {
@@ -138,10 +140,15 @@ struct Acc {
 };
 
 // The sweep's constants from the FP64 parameters, formed in the instance's
-// own arithmetic (FP32: hardware log2 / rcp, about 1 ulp).
-template <typename T = float>
+// own arithmetic (FP32: hardware log2 / rcp, about 1 ulp).  UNI: the whole
+// wave forms the same constants and keeps them wave-uniform (scalar
+// registers); without it one lane forms its own stamp's constants (the
+// batched form), with the same arithmetic.
+template <typename T = float, bool UNI = true>
 __device__ __forceinline__ Trial<T> make_trial(const double* p, int model, double beta) {
-  using A = Arith<T>;
+  struct A : Arith<T> {
+    static __device__ __forceinline__ T uni(T v) { return UNI ? Arith<T>::uni(v) : v; }
+  };
   Trial<T> t;
   const T e1 = (T)p[2], e2 = (T)p[3];
   t.x0 = A::uni((T)p[0]);
@@ -212,6 +219,13 @@ __device__ __forceinline__ Trial<T> make_trial(const double* p, int model, doubl
 // 64 / side rows at a time, and the trip count is the same for all lanes.
 constexpr int kLayoutAny = 0;
 constexpr int kLayoutRows = 1;
+// kLayoutStaged: any side, the stamp passed through an LDS buffer of
+// kStageBytes in blocks (one burst of loads per block, so a sweep of a stamp
+// that is not in the caches waits on memory once per block, not once per
+// pixel); pixel order per lane and the partial-sum cadence are those of
+// kLayoutAny, so the sums are the same bit for bit.
+constexpr int kLayoutStaged = 2;
+constexpr int kStageBytes = 8192;
 __host__ __device__ inline constexpr bool rows_layout_fits(int side) {
   return side == 8 || side == 16 || side == 32 || side == 64;
 }
@@ -226,7 +240,7 @@ __host__ __device__ inline constexpr bool rows_layout_fits(int side) {
 template <int DT, int MODEL, uint32_t EM, int STRIDE = kWave, typename T = float,
           int LAYOUT = kLayoutAny>
 __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, const Trial<T>& t,
-                             Acc<EM, T>& acc, int tid = -1) {
+                             Acc<EM, T>& acc, int tid = -1, void* stage = nullptr) {
   using A = Arith<T>;
   constexpr int kFlush = sizeof(T) == 4 ? SHAPE_SWEEP_FLUSH : 0;
   acc.c2 = 0.0;
@@ -344,8 +358,8 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     }
   } else {
     int cnt = 0;
-    for_pixels<STRIDE>(st.side, [&](int k, int i, int j) {
-      const T d = (T)load_px<DT>(b.pixels, st.off, k, st.scale);
+    // pixel (i, j) with value d, in the lane-stride order of for_pixels
+    auto any_pixel = [&](const T d, int i, int j) {
       const T u1 = (T)j - t.x0, u2 = (T)i - t.y0;
       // (v1, v2) = S(e) u
       const T v1 = A::fma(t.a11, u1, t.a12 * u2), v2 = A::fma(t.a12, u1, t.a22 * u2);
@@ -358,7 +372,50 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
           cnt = 0;
         }
       }
-    }, tid);
+    };
+    if constexpr (LAYOUT == kLayoutStaged) {
+      using E = typename std::conditional<DT == SHAPE_F32, float, _Float16>::type;
+      constexpr int kBlk = kStageBytes / (int)sizeof(E);
+      static_assert(kBlk % (STRIDE * (kFlush > 0 ? kFlush : 1)) == 0,
+                    "blocks keep the partial-sum cadence");
+      auto stage_sync = [] {
+        if constexpr (STRIDE == kWave)
+          wave_sync();
+        else
+          __syncthreads();
+      };
+      E* buf = static_cast<E*>(stage);
+      const E* src = static_cast<const E*>(b.pixels) + st.off;
+      const int side = st.side, npix = st.npix;
+      const int t0 = tid < 0 ? (int)(threadIdx.x & (kWave - 1)) : tid;
+      int i = t0 / side, j = t0 - i * side;
+      const int di = STRIDE / side, dj = STRIDE - di * side;
+      int k = t0;
+#pragma unroll 1
+      for (int k0 = 0; k0 < npix; k0 += kBlk) {
+        const int nb = npix - k0 < kBlk ? npix - k0 : kBlk;
+        stage_sync();   // the previous block's reads are done
+#pragma unroll 8
+        for (int q = t0; q < nb; q += STRIDE) buf[q] = src[k0 + q];
+        stage_sync();
+#pragma unroll 1
+        for (; k < k0 + nb; k += STRIDE) {
+          const E e = buf[k - k0];
+          const T d = DT == SHAPE_F32 ? (T)(float)e : (T)((float)e * st.scale);
+          any_pixel(d, i, j);
+          i += di;
+          j += dj;
+          if (j >= side) {
+            j -= side;
+            ++i;
+          }
+        }
+      }
+    } else {
+      for_pixels<STRIDE>(st.side, [&](int k, int i, int j) {
+        any_pixel((T)load_px<DT>(b.pixels, st.off, k, st.scale), i, j);
+      }, tid);
+    }
   }
   flush();
   if constexpr (kFold) {
@@ -376,7 +433,8 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
 }
 
 // Reduce a sweep's per-lane partial sums over the wave and store them (FP64)
-// at dst: [0] = chi^2 sum, [1 + k] = (J^T r)_k, [9 + tri] = J^T J.  One
+// at dst (entry k at dst[k * stride]): [0] = chi^2 sum, [1 + k] = (J^T r)_k,
+// [9 + tri] = J^T J.  One
 // quantity at a time by wave sums, with scheduling barriers, so the
 // reductions do not all hold registers at once, and lane 0 stores.
 //
@@ -389,7 +447,8 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
 // J^T J where one wave sum per entry takes about 360; the 9 FP64 sums go the
 // same way (padded to 12, row k ends with entries 3k..3k+2).
 template <uint32_t EM, typename T = float>
-__device__ __forceinline__ void reduce_store(const Acc<EM, T>& acc, double* dst, int lane) {
+__device__ __forceinline__ void reduce_store(const Acc<EM, T>& acc, double* dst, int lane,
+                                             int64_t stride = 1) {
   if constexpr (sizeof(T) == 4 && popcount(EM) >= 6) {
     // chi^2 and J^T r (FP64), padded to 12: after the two swaps row k holds
     // entries 3k..3k+2 (dst[0] = chi^2, dst[1 + a] = (J^T r)_a)
@@ -412,7 +471,7 @@ __device__ __forceinline__ void reduce_store(const Acc<EM, T>& acc, double* dst,
     if ((lane & 15) == 15 && lane < 48) {
       const int base = 3 * (lane >> 4);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) dst[base + j] = u[j];
+      for (int j = 0; j < 3; ++j) dst[(base + j) * stride] = u[j];
     }
     __builtin_amdgcn_sched_barrier(0);
     float v[36];
@@ -432,7 +491,7 @@ __device__ __forceinline__ void reduce_store(const Acc<EM, T>& acc, double* dst,
     if ((lane & 15) == 15) {
       const int base = 9 + 9 * (lane >> 4);
 #pragma unroll
-      for (int j = 0; j < 9; ++j) dst[base + j] = (double)v[j];
+      for (int j = 0; j < 9; ++j) dst[(base + j) * stride] = (double)v[j];
     }
     return;
   }
@@ -445,18 +504,18 @@ __device__ __forceinline__ void reduce_store(const Acc<EM, T>& acc, double* dst,
   for (int a = 0; a < 8; ++a) {
     if (has(EM, a)) {
       const double v = wave_sum(acc.g[a]);
-      if (lane == 0) dst[1 + a] = v;
+      if (lane == 0) dst[(1 + a) * stride] = v;
     } else if (lane == 0) {
-      dst[1 + a] = 0.0;
+      dst[(1 + a) * stride] = 0.0;
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = a; c < 8; ++c) {
       if (has(EM, a) && has(EM, c)) {
         const T v = wave_sum(acc.A[tri(a, c)]);
-        if (lane == 0) dst[9 + tri(a, c)] = (double)v;
+        if (lane == 0) dst[(9 + tri(a, c)) * stride] = (double)v;
       } else if (lane == 0) {
-        dst[9 + tri(a, c)] = 0.0;
+        dst[(9 + tri(a, c)) * stride] = 0.0;
       }
       __builtin_amdgcn_sched_barrier(0);
     }

@@ -138,7 +138,7 @@ def test_queue_argument_errors(shape):
     c = shape.queue_cfg()
     assert c.team == 1 and c.grid == 0
     need = shape.queue_workspace_bytes(b.n)
-    assert need >= b.n * 448
+    assert need >= b.n * 1000
     assert shape.queue_workspace_bytes(10 ** 6) > 400 * 10 ** 6
     nb = C.c_size_t()
     assert L.shape_queue_workspace_bytes(-1, C.byref(nb)) == shape.EINVAL
@@ -159,6 +159,9 @@ def test_queue_argument_errors(shape):
     c2 = shape.queue_cfg(team=2, team_min_side=64)
     assert L.shape_queue_step(C.byref(b), C.byref(o4), C.byref(c2), out, need,
                               None) == shape.EUNSUPPORTED
+    assert L.shape_queue_drain(C.byref(b), C.byref(o), C.byref(c), out, need - 1,
+                               None) == shape.ENOMEM
+    assert L.shape_queue_drain(C.byref(b), C.byref(o), None, out, need, None) == shape.EINVAL
     g = C.c_void_p()
     assert L.shape_queue_graph_create(C.byref(b), C.byref(o), C.byref(c), out, need - 1,
                                       C.byref(g)) == shape.ENOMEM

@@ -36,6 +36,9 @@ if ROOT not in sys.path:
 # + 1 transcendental (a shared factor dm/dR^2, the N u products, eight
 # columns), J^T J 63, J^T r and chi^2 17.
 FLOP_PER_PIXEL_SWEEP = 124.0
+# The hot-path table's planning estimate of the same work: about 85 VALU
+# operations per pixel and sweep, 150 FLOP with FMA = 2.
+FLOP_PER_PIXEL_SWEEP_SURVEY = 150.0
 # Per pixel per iteration of the other stages (FMA = 2, transcendental = 1):
 # centroid sweep: offsets 2, R^2 3, weight 2, f W 2, three sums 5 -> 14;
 # moments sweep: offsets 2, products 3, R^2 5, weight 2, f W 2, eleven
@@ -109,22 +112,40 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def parity(np, shape, oracle, fit, ref, m):
+def fit_parity_block(fit, ref, batch, m, mask=0xFF):
+    """GPU fit vs the FP64 oracle on the first m stamps, by the parity rule of
+    tests/parity_util.py: bars on stamps both sides fit to the interior,
+    chi^2 / sigma_p / amplitudes there, every disagreement validated as a
+    minimum of the oracle's chi^2 no worse than the oracle's."""
+    import numpy as np
+    from parity_util import fit_parity
     g = {k: v[:m].cpu().numpy() for k, v in fit.items() if hasattr(v, "cpu")}
-    both = ((g["status"] & shape.ST_CONVERGED) != 0) & \
-           ((ref["status"][:, 2] & oracle.CONVERGED) != 0)
-    if not both.any():
-        return {"sample": m, "both_converged": 0, "within_bars": 0.0}
-    d = np.abs(g["p"][both] - ref["p"][both])
-    rel = np.abs(g["p"][both] / ref["p"][both] - 1)
-    ok = (d[:, :2].max(1) <= BARS["x"]) & (d[:, 2:4].max(1) <= BARS["e"]) & \
-         (rel[:, 4:6].max(1) <= BARS["rel"])
-    return {"sample": m, "both_converged": int(both.sum()),
-            "gpu_converged": int(((g["status"] & shape.ST_CONVERGED) != 0).sum()),
-            "max_dxy_px": float(d[:, :2].max()), "max_de": float(d[:, 2:4].max()),
-            "max_rel_re": float(rel[:, 4].max()), "max_rel_n": float(rel[:, 5].max()),
-            "max_rel_i0": float(rel[:, 6].max()), "max_rel_sky": float(rel[:, 7].max()),
-            "within_bars": float(ok.mean())}
+    g["status"] = np.stack([np.zeros(m, np.uint32), np.zeros(m, np.uint32),
+                            g["status"].astype(np.uint32)], 1)
+    st, failures = fit_parity(g, ref, batch, mask)
+    st.pop("alternatives", None)
+    st["failures"] = len(failures)
+    st["rule"] = ("bars |dxy|<=1e-3 px, |de|<=1e-4, rel Re,n<=1e-3 on stamps both fit to the "
+                  "interior; chi^2, sigma_p, I0, sky checked there; each stamp outside the bars "
+                  "must be a validated minimum of the oracle chi^2")
+    return st
+
+
+def sigma_units(p_a, p_b, perr, mask, both):
+    """|p_a - p_b| / sigma_p over the fitted parameters on stamps `both`:
+    p50, p99, max per parameter."""
+    import numpy as np
+    names = ["x0", "y0", "e1", "e2", "Re", "n", "I0", "sky"]
+    out = {}
+    for k in range(8):
+        if not (mask >> k) & 1:
+            continue
+        z = np.abs(p_a[both, k] - p_b[both, k]) / perr[both, k]
+        z = z[np.isfinite(z)]
+        if z.size:
+            out[names[k]] = [float(np.percentile(z, 50)), float(np.percentile(z, 99)),
+                             float(z.max())]
+    return out
 
 
 def main():
@@ -132,15 +153,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--count", type=int, default=None, help="stamps (default: all 262,144)")
+    ap.add_argument("--count", type=int, default=None, help="stamps (default: the whole workload)")
     ap.add_argument("--forms", default="plain,f16,f16_queue")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
-    ap.add_argument("--workload", default="sersic64h", choices=["sersic64h", "uneven", "stars32", "frames512", "plain32x",
+    ap.add_argument("--workload", default="sersic64h",
+                    choices=["sersic64h", "plain48", "uneven", "stars32", "frames512", "plain32x",
                              "sersic64"],
-                    help="uneven: 1,000,000 stamps of side 16-128 (80%% Sersic, 20%% Moffat), "
+                    help="plain48: 100,000 48x48 Sersic stamps, 8-parameter fit, cap 30; "
+                         "uneven: 1,000,000 stamps of side 16-128 (80%% Sersic, 20%% Moffat), "
                          "fused fit vs autotuned work queue; stars32: 1,048,576 32x32 Moffat "
                          "stars, sizes from weighted moments; frames512: 4,096 512x512 frames, "
                          "detection and 6 r50 cut-outs; plain32x: 262,144 32x32 Gaussian "
@@ -169,7 +192,11 @@ def main():
         return bench_profiled(args)
     if args.workload == "sersic64":
         return bench_adjoint(args)
+    wl = args.workload      # sersic64h (FP16 + FP32 copies) or plain48 (FP32)
+    side = 64 if wl == "sersic64h" else 48
     forms = [f for f in args.forms.split(",") if f]
+    if wl == "plain48":
+        forms = [f.replace("f16_queue", "queue") for f in forms if f != "f16"]
     # Stamps are generated (in worker processes) before this process touches
     # the GPU, so no worker is forked from a process with an initialised runtime.
     b16 = b32 = None
@@ -177,15 +204,16 @@ def main():
     if not args.copy_calibration:
         t = time.time()
         if any(f.startswith("f16") for f in forms):
-            b16 = synth.make("sersic64h", count=args.count)
-        if "plain" in forms:
-            b32 = synth.make("sersic64h", count=args.count, storage="f32")
+            b16 = synth.make(wl, count=args.count)
+        if "plain" in forms or "queue" in forms:
+            b32 = synth.make(wl, count=args.count, storage="f32")
         n = (b16 or b32).n
-        log("generated %d stamps (64x64) in %.1f s" % (n, time.time() - t))
+        log("generated %d stamps (%dx%d) in %.1f s" % (n, side, side, time.time() - t))
 
     import torch
 
     import paper_1203_0571_amd as shape
+    from paper_1203_0571_amd import autotune
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -201,24 +229,37 @@ def main():
         return
 
     opts = shape.default_opts()
-    qcfg = shape.queue_cfg(team=1)
     dbs = {}
     if b32 is not None:
         dbs["f32"] = shape.DeviceBatch.from_host(b32, dev)
     if b16 is not None:
         dbs["f16"] = shape.DeviceBatch.from_host(b16, dev)
     torch.cuda.synchronize()
+    storage = {"plain": "f32", "queue": "f32", "f16": "f16", "f16_queue": "f16"}
+    tuned = {}
+    for form in forms:
+        if form.endswith("queue"):
+            db = dbs[storage[form]]
+            r0, _, _ = shape.centroid(db, opts)
+            r1, _, _ = shape.moments(db, r0, opts)
+            t = time.time()
+            tuned[form] = autotune.tune_queue(db, r1, opts, use_cache=False)
+            log("autotune %s %.1f s: team %d, grid %d, drain at %.2f" % (
+                form, time.time() - t, tuned[form]["cfg"].team, tuned[form]["cfg"].grid,
+                tuned[form]["drain_frac"]))
 
-    def step(form, events=None):
-        db = dbs["f32" if form == "plain" else "f16"]
+    def step(form, events=None, want_perr=False):
+        db = dbs[storage[form]]
         rec0, _, _ = shape.centroid(db, opts)
         rec1, _, _ = shape.moments(db, rec0, opts)
         if events:
             events[0].record()
-        if form == "f16_queue":
-            fit = shape.fit_queue(db, rec=rec1, opts=opts, cfg=qcfg, use_graph=True)
+        if form.endswith("queue"):
+            fit = shape.fit_queue(db, rec=rec1, opts=opts, cfg=tuned[form]["cfg"], use_graph=True,
+                                  drain_at=int(tuned[form]["drain_frac"] * n),
+                                  want_perr=want_perr)
         else:
-            fit = shape.fit_sersic(db, rec=rec1, opts=opts)
+            fit = shape.fit_sersic(db, rec=rec1, opts=opts, want_perr=want_perr)
         if events:
             events[1].record()
         return fit
@@ -238,37 +279,39 @@ def main():
         fit_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
         sweeps = fit["sweeps"].cpu().numpy().astype(np.float64)
         status = fit["status"].cpu().numpy()
-        pixel_sweeps = float(sweeps.sum()) * 64 * 64
-        results[form] = dict(fit=fit, elapsed=elapsed, fit_ms=fit_ms,
-                             objs=n * args.steps / elapsed, pixel_sweeps=pixel_sweeps,
+        pixel_sweeps = float(sweeps.sum()) * side * side
+        results[form] = dict(elapsed=elapsed, fit_ms=fit_ms, objs=n * args.steps / elapsed,
+                             pixel_sweeps=pixel_sweeps,
                              conv=float(((status & shape.ST_CONVERGED) != 0).mean()),
                              mean_sweeps=float(sweeps.mean()))
         log("%-10s %d steps in %.3f s: %.0f objects/s; fit %.3f ms/step, %.4f converged"
             % (form, args.steps, elapsed, results[form]["objs"], fit_ms, results[form]["conv"]))
+    # outputs with sigma_p for the parity leg (untimed)
+    for form in forms:
+        results[form]["fit"] = step(form, want_perr=True)
+    torch.cuda.synchronize()
 
     par, cpu = {}, None
     if not args.no_cpu:
         import oracle
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
         m = min(args.cpu_sample, n)
-        refs = {}
-        if b16 is not None:
+        refs, heads = {}, {}
+        for key, bb in (("f16", b16), ("f32", b32)):
+            if bb is None:
+                continue
+            heads[key] = bb.head(m)
             t = time.perf_counter()
-            refs["f16"] = oracle.pipeline(b16.head(m), oracle.opts())
+            refs[key] = oracle.pipeline(heads[key], oracle.opts())
             cpu_s = time.perf_counter() - t
-            cpu = {"value": round(m / cpu_s, 2), "unit": "objects/s",
-                   "cores": int(refs["f16"]["threads"]), "kind": "oracle",
-                   "sample": "first %d stamps of the workload (FP16 pixels dequantised to FP64), "
-                             "FP64 oracle, LM tol 1e-9, cap 200, %.1f s" % (m, cpu_s)}
-            log("cpu oracle: %d stamps in %.1f s on %d threads" % (m, cpu_s, refs["f16"]["threads"]))
-        if b32 is not None:
-            t = time.perf_counter()
-            refs["f32"] = oracle.pipeline(b32.head(m), oracle.opts())
+            log("cpu oracle (%s pixels): %d stamps in %.1f s on %d threads"
+                % (key, m, cpu_s, refs[key]["threads"]))
             if cpu is None:
-                cpu_s = time.perf_counter() - t
                 cpu = {"value": round(m / cpu_s, 2), "unit": "objects/s",
-                       "cores": int(refs["f32"]["threads"]), "kind": "oracle",
-                       "sample": "first %d stamps of the workload (FP32), FP64 oracle, "
-                                 "LM tol 1e-9, cap 200, %.1f s" % (m, cpu_s)}
+                       "cores": int(refs[key]["threads"]), "kind": "oracle",
+                       "sample": "first %d stamps of the workload (%s pixels, as FP64), FP64 "
+                                 "oracle pipeline, LM tol 1e-9, cap 200, %.1f s"
+                                 % (m, "FP16-stored" if key == "f16" else "FP32", cpu_s)}
         if cpu is not None:
             # the same oracle on one thread, comparable with the paper's
             # single-core timings (0.1 s centroid + ellipticity, 0.5 s fit per
@@ -280,26 +323,52 @@ def main():
             cpu["one_thread"] = {"value": round(m1 / s1, 2), "unit": "objects/s",
                                  "sample": "first %d stamps, %.1f s" % (m1, s1)}
             log("cpu oracle, one thread: %d stamps in %.1f s" % (m1, s1))
-        for form, r in results.items():
-            par[form] = parity(np, shape, oracle, r["fit"], refs["f32" if form == "plain" else "f16"], m)
+        done = {}
+        for form in forms:
+            key = storage[form]
+            fit = results[form]["fit"]
+            same = next((f for f in done if storage[f] == key and all(
+                torch.equal(fit[k], results[f]["fit"][k]) for k in ("p", "chi2", "status"))), None)
+            if same:
+                par[form] = dict(par[same], identical_to=same)
+                continue
+            t = time.perf_counter()
+            par[form] = fit_parity_block(fit, refs[key], heads[key], m)
+            log("parity %s: %d failures, %d validated alternative minima (%.1f s)"
+                % (form, par[form]["failures"], par[form]["validated_alternative_minima"],
+                   time.perf_counter() - t))
+            done[form] = True
         if "f16" in refs and "f32" in refs:
-            # effect of FP16 storage itself: oracle on FP16 pixels vs oracle on FP32 pixels
+            # the FP16 storage itself: oracle on FP16 pixels vs oracle on FP32
+            # pixels, in units of the standard errors, where both fit to the interior
             a, c = refs["f16"], refs["f32"]
-            both = ((a["status"][:, 2] & 1) != 0) & ((c["status"][:, 2] & 1) != 0)
-            d = np.abs(a["p"][both] - c["p"][both])
-            rel = np.abs(a["p"][both] / c["p"][both] - 1)
-            pr = lambda v: float(np.percentile(v, 99))
-            par["fp16_storage_effect_p99"] = {
-                "dxy_px": pr(d[:, :2].max(1)), "de": pr(d[:, 2:4].max(1)),
-                "rel_re": pr(rel[:, 4]), "rel_n": pr(rel[:, 5]), "rel_i0": pr(rel[:, 6]),
-                "rel_sky": pr(rel[:, 7])}
+            cl = lambda st: ((st[:, 2] & 1) != 0) & ((st[:, 2] & oracle.AT_BOUND) == 0)
+            both = cl(a["status"]) & cl(c["status"])
+            par["fp16_storage_effect_in_sigma"] = {
+                "stamps": int(both.sum()), "p50_p99_max": sigma_units(a["p"], c["p"], c["perr"],
+                                                                      0xFF, both)}
+            # the error each FP16 form makes against the oracle on FP32 pixels
+            for form in forms:
+                if storage[form] != "f16":
+                    continue
+                g = {k: v[:m].cpu().numpy() for k, v in results[form]["fit"].items()
+                     if hasattr(v, "cpu")}
+                gst = g["status"].astype(np.uint32)
+                bg = ((gst & 1) != 0) & ((gst & oracle.AT_BOUND) == 0) & cl(c["status"])
+                par[form]["vs_oracle_on_fp32_pixels_in_sigma"] = {
+                    "stamps": int(bg.sum()),
+                    "p50_p99_max": sigma_units(g["p"].astype(np.float64), c["p"], c["perr"],
+                                               0xFF, bg)}
 
-    ok = [f for f in results if f not in par or par[f]["within_bars"] >= 0.99]
+    ok = [f for f in results if f not in par or par[f]["failures"] == 0]
     chosen = max(ok or list(results), key=lambda f: results[f]["objs"])
     rc = results[chosen]
     achieved = rc["pixel_sweeps"] * FLOP_PER_PIXEL_SWEEP / (rc["fit_ms"] * 1e-3) / 1e12
+    achieved_s = rc["pixel_sweeps"] * FLOP_PER_PIXEL_SWEEP_SURVEY / (rc["fit_ms"] * 1e-3) / 1e12
+    wl_desc = ("sersic64h: 262,144 x 64x64 Sersic stamps, seed 0" if wl == "sersic64h" else
+               "plain48: 100,000 x 48x48 Sersic stamps, seed 0")
     line = {
-        "metric": "objects fitted/sec (64x64 Sersic stamps)",
+        "metric": "objects fitted/sec (%dx%d Sersic stamps)" % (side, side),
         "value": round(rc["objs"], 1),
         "unit": "objects/s",
         "n_gpus": 1,
@@ -311,10 +380,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "sersic64h: 262,144 x 64x64 Sersic stamps, seed 0",
-                   "stamps": n, "chosen_form": chosen, "free_params": 8,
-                   "storage": "f32" if chosen == "plain" else "f16 x per-stamp scale",
+        "config": {"workload": wl_desc, "stamps": n, "chosen_form": chosen, "free_params": 8,
+                   "storage": "f16 x per-stamp scale" if storage[chosen] == "f16" else "f32",
                    "max_iter_lm": opts.max_iter_lm,
+                   "chosen_by": "most objects/s among the forms whose parity sample has no "
+                                "failing stamp under the parity rule",
                    "forms": {f: {"objects_per_s": round(r["objs"], 1),
                                  "ms_per_step": round(r["elapsed"] / args.steps * 1e3, 4),
                                  "fit_ms": round(r["fit_ms"], 4),
@@ -324,14 +394,25 @@ def main():
         "roofline": {"bound": "alu", "kernel": "fit (" + chosen + ")",
                      "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                     "traffic": fit_traffic_bytes(chosen) if chosen in ("plain", "f16") else None,
+                     "traffic": fit_traffic_bytes(chosen) if (chosen in ("plain", "f16") and
+                                                              wl == "sersic64h") else None,
                      "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "launch_ms": round(rc["fit_ms"], 4),
                      "flop_per_pixel_sweep": FLOP_PER_PIXEL_SWEEP,
-                     "pixel_sweeps_per_launch": rc["pixel_sweeps"]},
+                     "flop_count": "the sweep's own formulation, FMA = 2, transcendental = 1",
+                     "pixel_sweeps_per_launch": rc["pixel_sweeps"],
+                     "survey_count": {"flop_per_pixel_sweep": FLOP_PER_PIXEL_SWEEP_SURVEY,
+                                      "achieved": round(achieved_s, 3),
+                                      "frac": round(achieved_s / ALU_PEAK_TFLOPS, 4),
+                                      "note": "the hot-path table's estimate of ~85 VALU ops "
+                                              "per pixel-sweep, FMA = 2"}},
     }
     if cpu:
         line["cpu_baseline"] = cpu
+    if tuned:
+        line["config"]["queue_cfg"] = {f: dict(team=t["cfg"].team, team_min_side=t["cfg"].team_min_side,
+                                               grid=t["cfg"].grid, drain_frac=t["drain_frac"])
+                                       for f, t in tuned.items()}
     # context, not the target: the paper's single-core timings for this path
     line["paper_context"] = {"hardware": "single-core 2.2 GHz Intel CPU (Sec. 4.1)",
                              "seconds_per_object": {"centroid_and_ellipticity": 0.1,

@@ -445,34 +445,42 @@ def bench_uneven(args):
     dev = torch.device("cuda:0")
     db = shape.DeviceBatch.from_host(b, dev)
     opts = shape.default_opts()
-    rec0, _, _ = shape.centroid(db, opts)
-    rec1, _, _ = shape.moments(db, rec0, opts)
-    t = time.time()
-    tuned = autotune.tune_queue(db, rec1, opts, use_cache=False)
-    cfg, drain_at = tuned["cfg"], int(tuned["drain_frac"] * db.n)
-    log("autotune %.1f s: best %s drain %.2f" % (time.time() - t, dict(team=cfg.team, team_min_side=cfg.team_min_side, grid=cfg.grid), tuned["drain_frac"]))
+    # forms: "fused" (one launch in input order) and "queue"; --forms picks
+    # among them (both when it names neither)
+    forms = [f for f in args.forms.split(",") if f in ("fused", "queue")] or ["fused", "queue"]
+    cfg, drain_at = None, 0
+    if "queue" in forms:
+        rec0, _, _ = shape.centroid(db, opts)
+        rec1, _, _ = shape.moments(db, rec0, opts)
+        t = time.time()
+        tuned = autotune.tune_queue(db, rec1, opts, use_cache=False)
+        cfg, drain_at = tuned["cfg"], int(tuned["drain_frac"] * db.n)
+        log("autotune %.1f s: best %s drain %.2f" % (time.time() - t, dict(team=cfg.team, team_min_side=cfg.team_min_side, grid=cfg.grid), tuned["drain_frac"]))
 
     def step(form, ev=None):
-        r0, _, _ = shape.centroid(db, opts)
-        r1, _, _ = shape.moments(db, r0, opts)
         if ev:
             ev[0].record()
+        r0, _, _ = shape.centroid(db, opts)
+        if ev:
+            ev[1].record()
+        r1, _, _ = shape.moments(db, r0, opts)
+        if ev:
+            ev[2].record()
         if form == "queue":
             fit = shape.fit_queue(db, rec=r1, opts=opts, cfg=cfg, use_graph=True,
                                   drain_at=drain_at)
         else:
             fit = shape.fit_sersic(db, rec=r1, opts=opts)
         if ev:
-            ev[1].record()
+            ev[3].record()
         return fit
 
     res = {}
-    for form in ("fused", "queue"):
+    for form in forms:
         for _ in range(args.warmup):
             step(form)
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
         t0 = time.perf_counter()
         for k in range(args.steps):
             fit = step(form, evs[k])
@@ -480,12 +488,14 @@ def bench_uneven(args):
         el = time.perf_counter() - t0
         st = fit["status"].cpu().numpy()
         sw = fit["sweeps"].cpu().numpy().astype(np.float64)
+        span = lambda i: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs]))
         res[form] = dict(objs=b.n * args.steps / el, ms=el / args.steps * 1e3,
-                         fit_ms=float(np.mean([x.elapsed_time(y) for x, y in evs])),
+                         centroid_ms=span(0), moments_ms=span(1), fit_ms=span(2),
                          conv=float(((st & shape.ST_CONVERGED) != 0).mean()),
                          px_sweeps=float((sw * b.sides.astype(np.float64) ** 2).sum()))
-        log("%-6s %.0f objects/s, fit %.2f ms, converged %.4f"
-            % (form, res[form]["objs"], res[form]["fit_ms"], res[form]["conv"]))
+        log("%-6s %.0f objects/s, centroid %.2f ms, moments %.2f ms, fit %.2f ms, converged %.4f"
+            % (form, res[form]["objs"], res[form]["centroid_ms"], res[form]["moments_ms"],
+               res[form]["fit_ms"], res[form]["conv"]))
     best = max(res, key=lambda f: res[f]["objs"])
     r = res[best]
     achieved = r["px_sweeps"] * FLOP_PER_PIXEL_SWEEP / (r["fit_ms"] * 1e-3) / 1e12
@@ -495,8 +505,8 @@ def bench_uneven(args):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": "uneven: %d stamps, seed 0" % b.n, "chosen_form": best,
-                       "queue_cfg": dict(team=cfg.team, team_min_side=cfg.team_min_side,
-                                         grid=cfg.grid),
+                       "queue_cfg": (dict(team=cfg.team, team_min_side=cfg.team_min_side,
+                                          grid=cfg.grid) if cfg else None),
                        "forms": {f: {k: round(v, 4) for k, v in x.items()} for f, x in res.items()}},
             "roofline": {"bound": "alu", "kernel": "fit (" + best + ")",
                          "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS,

@@ -82,6 +82,13 @@ __device__ inline double add(double v) {
   const int hi = mov<CTRL, ROWS>((int)(uint32_t)(u >> 32));
   return v + __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
+template <int CTRL, int ROWS>
+__device__ inline long long add(long long v) {
+  const uint64_t u = (uint64_t)v;
+  const int lo = mov<CTRL, ROWS>((int)(uint32_t)u);
+  const int hi = mov<CTRL, ROWS>((int)(uint32_t)(u >> 32));
+  return (long long)(u + (((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
 }  // namespace dpp
 
 template <class T>
@@ -103,6 +110,12 @@ __device__ inline double wave_sum(double v) {
   const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, 63);
   const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ inline long long readlane64(long long v, int lane) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  return (long long)(((uint64_t)hi << 32) | lo);
 }
 __device__ inline bool wave_any(bool p) { return __any(p); }
 

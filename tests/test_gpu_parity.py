@@ -169,6 +169,43 @@ def test_edge_cases(shape):
     assert out["p"].shape == (0, 8)
 
 
+def test_every_side_stages(shape):
+    """Centroid and moments on one batch holding every side from 4 to 128
+    (two stamps each, mixed in order): every register layout of the any-side
+    forms (one wave up to side 64, a team of four above) against the oracle."""
+    rng = np.random.default_rng(11)
+    stamps, sig = [], []
+    for side in range(4, 129):
+        for k in range(2):
+            re = max(0.6, side / 8.0 * rng.uniform(0.7, 1.3))
+            c = (side - 1) / 2.0 + rng.uniform(-0.3, 0.3, 2) * max(1.0, side / 16.0)
+            e = rng.uniform(-0.2, 0.2, 2)
+            p = np.array([c[0], c[1], e[0], e[1], re, rng.uniform(0.7, 3.0), 400.0, 0.0])
+            img = synth.render_sersic(side, p)[0] + 10.0
+            stamps.append(img + rng.normal(0, 1.5, img.shape))
+            sig.append(1.5)
+    order = rng.permutation(len(stamps))
+    b = _custom_batch([stamps[i] for i in order], [sig[i] for i in order])
+    o = shape.default_opts()
+    g = run_gpu(shape, b, o)
+    ref = oracle.pipeline(b, oracle_opts_like(o, max_iter_lm=1))
+    st_g, st_o = g["status"].astype(np.uint32), ref["status"]
+    assert (st_g[:, 0] == st_o[:, 0]).mean() >= 0.99
+    assert (st_g[:, 1] == st_o[:, 1]).mean() >= 0.98
+    lost = ((st_g[:, 0] | st_o[:, 0]) & oracle.LOST) != 0
+    ok0 = ~lost
+    assert ok0.mean() > 0.95
+    cg, mo = g["centroid"], ref["mom"]
+    assert np.abs(cg[ok0, :2] - ref["xy"][ok0]).max() <= BAR_X
+    assert np.abs(cg[ok0, 5] / mo[ok0, 5] - 1).max() <= 1e-5      # r50
+    assert np.abs(cg[ok0, 4] / mo[ok0, 4] - 1).max() <= 1e-5      # sigma_w
+    both = ((st_g[:, 1] & st_o[:, 1]) & oracle.CONVERGED) != 0
+    assert both.mean() > 0.9
+    mg = g["moments"]
+    assert np.abs(mg[both, :2] - mo[both, :2]).max() <= BAR_X
+    assert np.abs(mg[both, 2:4] - mo[both, 2:4]).max() <= BAR_E
+
+
 def test_deterministic(shape):
     b = synth.make("plain48", count=512)
     g1 = run_gpu(shape, b)

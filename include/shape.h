@@ -184,8 +184,8 @@ int shape_moments(const shape_batch* batch, const shape_opts* opts, const float*
  * complement of the amplitude block of J^T J, in FP64 on the device.  Moffat
  * stamps (model = 1) are fitted with beta fixed at opts->moffat_beta.
  *   p_init [n][8] in, or NULL: start from rec (x0, y0, e1, e2 of the moments,
- *          Re = the record's size, or r50 where it is NaN (Moffat
- *          rd = r50 / sqrt(2^(1/beta) - 1)), n = n0)
+ *          Re = the record's size, or r50 where it is NaN (Moffat: the
+ *          rd of half-light radius r50, r50 / sqrt(2^(1/(beta-1)) - 1)), n = n0)
  *   rec    [n][9] in (from shape_moments), used when p_init is NULL
  *   p_out  [n][8] out; chi2 [n] out; perr [n][8] out or NULL (sqrt of the
  *          diagonal of (J^T J / sigma^2)^-1 over the fitted parameters)

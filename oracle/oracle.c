@@ -819,8 +819,10 @@ void orc_star_moments(const double* img, int side, double sky, double xc, double
 /* Whole per-object procedure over a batch (Sec. 4.1, the paragraph on the   */
 /* starting point): starting estimates, centroid from the brightest pixel,   */
 /* joint centroid + ellipticity, then the profile fit from                   */
-/* (x0, y0, g) of the moments, Re = r50 (Moffat: rd = r50 / sqrt(2^(1/beta)  */
-/* - 1), the Gaussian-equivalent width), n = n0 (Moffat: beta fixed), and     */
+/* (x0, y0, g) of the moments, Re = the moments' size or r50 (Moffat: the    */
+/* rd whose half-light radius is r50: the flux of (1 + R^2/rd^2)^-beta       */
+/* inside R is 1 - (1 + R^2/rd^2)^(1-beta) of the total, so                  */
+/* rd = r50 / sqrt(2^(1/(beta-1)) - 1)), n = n0 (Moffat: beta fixed), and    */
 /* (I0, sky) solved linearly.                                                 */
 /* ------------------------------------------------------------------------ */
 int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
@@ -880,7 +882,7 @@ int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
       pi[4] = isfinite(mo[6]) ? mo[6] : r50;
       pi[5] = o->n0;
     } else {
-      pi[4] = r50 / sqrt(pow(2.0, 1.0 / o->moffat_beta) - 1.0);
+      pi[4] = r50 / sqrt(pow(2.0, 1.0 / (o->moffat_beta - 1.0)) - 1.0);
       pi[5] = o->moffat_beta;
     }
     if (pi[4] < 0.1) pi[4] = 0.1;

@@ -282,7 +282,9 @@ __device__ __forceinline__ LmState start_point(const KOpts& o, const Stamp& st, 
       p[4] = __builtin_isfinite(size) ? size : r50;
       p[5] = o.n0;
     } else {
-      p[4] = r50 / sqrt(exp2(1.0 / o.moffat_beta) - 1.0);
+      // the Moffat of half-light radius r50 (beta > 1: the enclosed flux is
+      // 1 - (1 + R^2 / rd^2)^(1 - beta) of the total)
+      p[4] = r50 / sqrt(exp2(1.0 / (o.moffat_beta - 1.0)) - 1.0);
       p[5] = o.moffat_beta;
     }
     p[4] = fmin(fmax(p[4], 0.1), (double)st.side);

@@ -64,6 +64,25 @@ def test_sersic64h_full(shape, storage, queue):
     assert ((g["status"][:, 2] & shape.ST_CONVERGED) != 0).mean() > 0.85
 
 
+@pytest.mark.parametrize("queue", [False, True])
+def test_plain48_full(shape, queue):
+    """100,000 x 48^2 Sersic stamps, 8 parameters, LM cap 30: the bench's two
+    forms (fused, and the work queue with one hipGraph replay per LM
+    iteration); 48 does not divide 64, so the stages take the any-side
+    register layout."""
+    b = synth.make("plain48")
+    db = shape.DeviceBatch.from_host(b, "cuda:0")
+    o = shape.default_opts()
+    g = _gpu_pipeline(shape, db, o, shape.queue_cfg(team=1) if queue else None)
+    idx = np.sort(np.random.default_rng(16).choice(b.n, SAMPLE, replace=False))
+    sub = _subset(b, idx)
+    ref = oracle.pipeline(sub, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
+    r = compare({k: v[idx] for k, v in g.items()}, ref, 0xFF, "plain48 queue=%s" % queue, batch=sub)
+    assert r["centroid_dxy"] <= 1e-3 and r["moments_dxy"] <= 1e-3 and r["moments_de"] <= 1e-4, r
+    check_fit(r, 0.85)
+    assert ((g["status"][:, 2] & shape.ST_CONVERGED) != 0).mean() > 0.85
+
+
 def test_uneven_full(shape):
     """1,000,000 uneven stamps (side 16-128, 20% Moffat): fused fit and the
     work queue with teams of two waves for sides >= 64."""

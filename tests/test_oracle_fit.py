@@ -220,3 +220,27 @@ def test_unprofiled_and_profiled_reach_the_same_minimum(mask):
         free = [k for k in range(8) if mask >> k & 1]
         assert np.max(np.abs(g[free] * scl[free])) < 1e-5 * max(r0["chi2"], 1.0)
     assert agree >= 8
+
+
+def test_moffat_start_has_half_light_radius_r50():
+    """The pipeline starts a Moffat fit at the rd whose half-light radius is
+    the growth-curve r50 (beta fixed).  Pinned to the profile itself: the
+    flux of (1 + R^2/rd^2)^-beta inside R = r50, integrated numerically, is
+    half the total.  (With LM cap 0 the fit returns its starting point.)"""
+    from scipy.integrate import quad
+    o = oracle.opts(max_iter_lm=0)
+    b = synth.make("uneven", count=256)
+    ref = oracle.pipeline(b, o)
+    beta = o.moffat_beta
+    m = np.flatnonzero((b.model == 1) & np.isfinite(ref["mom"][:, 5]))
+    checked = 0
+    for s in m:
+        r50, rd = ref["mom"][s, 5], ref["p"][s, 4]
+        if not (0.1 < rd < b.sides[s]):
+            continue   # clamped to the box
+        prof = lambda R: (1.0 + R * R / (rd * rd)) ** -beta * 2.0 * np.pi * R
+        inner = quad(prof, 0.0, r50, epsabs=0, epsrel=1e-12)[0]
+        total = quad(prof, 0.0, np.inf, epsabs=0, epsrel=1e-12)[0]
+        assert inner / total == pytest.approx(0.5, abs=1e-9), s
+        checked += 1
+    assert checked >= 20

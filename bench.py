@@ -585,6 +585,26 @@ def bench_stars(args):
                          "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
                          "launch_ms": round(ms[dom], 4)}}
+    # the paper's remedy for the rd-beta degeneracy (Sec. 4.2.2): beta fixed,
+    # here at the workload's mean (3.75), rd and I0 from r0 and r2
+    r1 = shape.moments(db, shape.centroid(db, opts)[0], opts)[0]
+    fb = []
+    for k in range(args.warmup + args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fout, fit_, fst = shape.star_moments_beta(db, r1, 3.75, 1e-4, 20)
+        e1.record()
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            fb.append(e0.elapsed_time(e1))
+    fstv = fst.cpu().numpy()
+    line["config"]["fixed_beta"] = {
+        "beta": 3.75, "kernel_ms": round(float(np.mean(fb)), 4),
+        "mean_iters": round(float(fit_.float().mean().item()), 3),
+        "converged_fraction": round(float(((fstv & shape.ST_CONVERGED) != 0).mean()), 4),
+        "free_beta_status": {k: round(float(((stv & getattr(shape, "ST_" + k)) != 0).mean()), 4)
+                             for k in ("CONVERGED", "SINGULAR", "MAX_ITER", "NONPOSITIVE_FLUX")}}
+    log("fixed beta: %.3f ms, converged %.4f" % (np.mean(fb), line["config"]["fixed_beta"]["converged_fraction"]))
     if not args.no_cpu:
         import oracle
         m = min(args.cpu_sample * 16, b.n)

@@ -234,13 +234,29 @@ int shape_chi2_bwd(const shape_batch* batch, const float* params, const float* g
  * sets w to the new size and repeats until the fractional change of the size
  * is below tol (the paper: 1e-4) or after max_iter steps (the paper: 20).
  * The weight starts at sigma_w of rec (Gaussian) or r50/sqrt(sqrt(2) - 1), the
- * beta = 3 Moffat with the record's r50 (Moffat).
+ * beta = 3 Moffat whose half-light radius is the record's r50 (Moffat).
  *   out [n][4] out: sigma or rd, beta (0 for Gaussian), I0, r0 of the last step
  *   iters, status [n] out.
  */
 int shape_star_moments(const shape_batch* batch, int32_t profile, const float* rec, double tol,
                        int32_t max_iter, float* out, int32_t* iters, uint32_t* status,
                        void* stream);
+
+/*
+ * Moffat star sizes with beta fixed (Sec. 4.2.2: the paper's way out of the
+ * rd-beta degeneracy and of the pixelation bias of faint stars is to measure
+ * beta on bright stars and fix it for the others).  The same weight
+ * W = (1 + R^2/w^2)^-3 and iteration as profile 1 of shape_star_moments, with
+ * rd = sqrt(r2/r0 (beta + 1)) and I0 = r0 (beta + 2)/(pi rd^2) for the given
+ * beta (r4 is not used, so the step cannot become singular).  The weight
+ * starts at the rd whose half-light radius is the record's r50,
+ * r50 / sqrt(2^(1/(beta-1)) - 1).
+ *   beta in (1, 1e6]; out [n][4]: rd, beta, I0, r0; iters, status [n] out.
+ * Same arguments, ownership and errors as shape_star_moments otherwise.
+ */
+int shape_star_moments_beta(const shape_batch* batch, double beta, const float* rec, double tol,
+                            int32_t max_iter, float* out, int32_t* iters, uint32_t* status,
+                            void* stream);
 
 /* ------------------------------------------------------------------------
  * Work-queue form of shape_fit_sersic for large batches, uneven stamps (any

@@ -26,6 +26,7 @@ LOST = 0x200
 
 SERSIC = 0
 MOFFAT = 1
+MOFFAT_BETA = 2     # star estimator: Moffat with beta fixed
 
 
 class Opts(C.Structure):
@@ -80,7 +81,7 @@ def lib():
         L.orc_fit.argtypes = [d, C.c_int, C.c_double, C.c_int, d, C.POINTER(Opts), d, d,
                               C.POINTER(C.c_int), C.POINTER(C.c_uint32), d]
         L.orc_star_moments.argtypes = [d, C.c_int, C.c_double, C.c_double, C.c_double, d,
-                                       C.c_int, C.c_double, C.c_double, C.c_int, d,
+                                       C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, d,
                                        C.POINTER(C.c_int), C.POINTER(C.c_uint32)]
         L.orc_pipeline.restype = C.c_int
         L.orc_pipeline.argtypes = [C.c_int64, d, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -90,7 +91,7 @@ def lib():
                                        C.POINTER(C.c_uint32)]
         L.orc_star_pipeline.restype = C.c_int
         L.orc_star_pipeline.argtypes = [C.c_int64, d, C.c_void_p, C.c_void_p, C.POINTER(Opts),
-                                        C.c_int, C.c_double, C.c_int, d, C.c_void_p,
+                                        C.c_int, C.c_double, C.c_double, C.c_int, d, C.c_void_p,
                                         C.c_void_p, C.c_int]
         _lib = L
     return _lib
@@ -212,14 +213,15 @@ def fit(img, sigma, p_init, kind=SERSIC, o=None):
     return dict(p=out, chi2=c2.value, iters=it.value, status=st.value, perr=perr)
 
 
-def star_moments(img, sky, xc, yc, g, kind, w0, tol=1e-4, max_iter=20):
-    """Sec. 4.2 star estimators; kind SERSIC = Gaussian star, MOFFAT = Moffat."""
+def star_moments(img, sky, xc, yc, g, kind, w0, tol=1e-4, max_iter=20, beta=3.0):
+    """Sec. 4.2 star estimators; kind SERSIC = Gaussian star, MOFFAT = Moffat,
+    MOFFAT_BETA = Moffat with beta fixed at `beta`."""
     img = _f64(img)
     gg = _f64(g)
     out = np.zeros(6)
     it, st = C.c_int(), C.c_uint32(0)
     lib().orc_star_moments(_dp(img), img.shape[0], float(sky), float(xc), float(yc), _dp(gg),
-                           int(kind), float(w0), float(tol), int(max_iter), _dp(out),
+                           int(kind), float(beta), float(w0), float(tol), int(max_iter), _dp(out),
                            C.byref(it), C.byref(st))
     return dict(size=out[0], beta=out[1], I0=out[2], r0=out[3], r2=out[4], r4=out[5],
                 iters=it.value, status=st.value)
@@ -249,9 +251,10 @@ def pipeline(batch, o=None, threads=0, pixels_f64=None):
                 threads=used)
 
 
-def star_pipeline(batch, kind, tol=1e-4, max_iter=20, o=None, threads=0):
+def star_pipeline(batch, kind, tol=1e-4, max_iter=20, o=None, threads=0, beta=3.0):
     """Star sizes over a synth.Batch (Sec. 4.2) after the centroid and moments
-    stages; out[n, 6] = (size, beta, I0, r0, r2, r4)."""
+    stages; out[n, 6] = (size, beta, I0, r0, r2, r4).  kind MOFFAT_BETA fixes
+    beta at `beta`."""
     o = o or opts()
     n = batch.n
     pix = _f64(batch.dequantised_f64())
@@ -261,7 +264,7 @@ def star_pipeline(batch, kind, tol=1e-4, max_iter=20, o=None, threads=0):
     iters = np.zeros(n, np.int32)
     status = np.zeros(n, np.uint32)
     used = lib().orc_star_pipeline(n, _dp(pix), offs.ctypes.data, sides.ctypes.data, C.byref(o),
-                                   int(kind), float(tol), int(max_iter), _dp(out),
+                                   int(kind), float(beta), float(tol), int(max_iter), _dp(out),
                                    iters.ctypes.data, status.ctypes.data, int(threads))
     return dict(out=out, iters=iters, status=status, threads=used)
 

@@ -754,6 +754,10 @@ void orc_fit(const double* img, int side, double sigma, int kind, const double* 
 /* give beta = 1 / (r4 r0 / (2 r2^2) - 1), rd = sqrt(r2 / r0 (beta + 1)),   */
 /* I0 = r0 (beta + 2) / (pi rd^2) (eqs. mofbetaiter, mofrditer, mofI0iter); */
 /* rdw is iterated to rd the same way.                                       */
+/* Moffat with beta fixed (the paper's remedy for the rd-beta degeneracy:   */
+/* beta measured on bright stars and fixed for fainter ones): the same      */
+/* weight, rd = sqrt(r2 / r0 (beta + 1)) and I0 = r0 (beta + 2) / (pi rd^2)  */
+/* with the given beta; r4 is not used.                                      */
 /* out: [0] sigma or rd, [1] beta (Moffat; 0 for Gaussian), [2] I0,          */
 /*      [3] r0, [4] r2, [5] r4 of the last evaluation.                       */
 /* ------------------------------------------------------------------------ */
@@ -779,20 +783,26 @@ static void star_sums(const double* img, int side, double sky, double xc, double
 }
 
 void orc_star_moments(const double* img, int side, double sky, double xc, double yc,
-                      const double* g, int kind, double w0, double tol, int max_iter,
-                      double* out, int* iters, uint32_t* status) {
-  /* kind: ORC_SERSIC selects the Gaussian star (n = 0.5), ORC_MOFFAT the Moffat */
+                      const double* g, int kind, double beta_fixed, double w0, double tol,
+                      int max_iter, double* out, int* iters, uint32_t* status) {
+  /* kind: ORC_SERSIC selects the Gaussian star (n = 0.5), ORC_MOFFAT the     */
+  /* Moffat, ORC_MOFFAT_BETA the Moffat with beta = beta_fixed                */
   double w = w0, r0 = 0, r2 = 0, r4 = 0, size = w0, beta = 0.0, I0 = 0.0;
+  if (kind == ORC_MOFFAT_BETA) beta = beta_fixed;
   int it = 0;
   *status = 0;
   while (it < max_iter) {
-    star_sums(img, side, sky, xc, yc, g, kind, w, &r0, &r2, &r4);
+    star_sums(img, side, sky, xc, yc, g, kind == ORC_SERSIC ? ORC_SERSIC : ORC_MOFFAT, w, &r0,
+              &r2, &r4);
     ++it;
     if (!(r0 > 0.0) || !(r2 > 0.0)) { *status |= ORC_NONPOSITIVE_FLUX; break; }
     double nsize;
     if (kind == ORC_SERSIC) {
       nsize = sqrt(r2 / r0);
       I0 = r0 / (ORC_PI * nsize * nsize);
+    } else if (kind == ORC_MOFFAT_BETA) {
+      nsize = sqrt(r2 / r0 * (beta + 1.0));
+      I0 = r0 * (beta + 2.0) / (ORC_PI * nsize * nsize);
     } else {
       double q = r4 * r0 / (2.0 * r2 * r2) - 1.0;
       if (!(q > 0.0)) { *status |= ORC_SINGULAR; break; }
@@ -901,11 +911,12 @@ int orc_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
 /* Star sizes over a batch (Sec. 4.2): starting estimates, centroid from the */
 /* brightest pixel, joint centroid + ellipticity, then the star estimator of */
 /* the given kind about that centre, starting from sigma_w (Gaussian) or     */
-/* r50 / sqrt(sqrt(2) - 1), the beta = 3 Moffat of that half-light radius.   */
+/* the Moffat of half-light radius r50, r50 / sqrt(2^(1/(beta-1)) - 1), with */
+/* beta = 3 (free beta) or the fixed beta.                                   */
 /* ------------------------------------------------------------------------ */
 int orc_star_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
-                      const int32_t* sides, const orc_opts* o, int kind, double tol,
-                      int max_iter, double* out, int32_t* iters, uint32_t* status,
+                      const int32_t* sides, const orc_opts* o, int kind, double beta_fixed,
+                      double tol, int max_iter, double* out, int32_t* iters, uint32_t* status,
                       int threads) {
   int used = 1;
 #ifdef _OPENMP
@@ -932,11 +943,12 @@ int orc_star_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
     orc_centroid(img, side, sky0, sigw, o, &x, &y, &it, &st);
     st = 0;
     orc_moments(img, side, sky0, sigw, r50, x, y, o, mo, &it, &st);
-    double w0 = kind == ORC_SERSIC ? sigw : r50 / sqrt(sqrt(2.0) - 1.0);
+    double bw = kind == ORC_MOFFAT_BETA ? beta_fixed : 3.0;
+    double w0 = kind == ORC_SERSIC ? sigw : r50 / sqrt(pow(2.0, 1.0 / (bw - 1.0)) - 1.0);
     int its;
     uint32_t sst;
-    orc_star_moments(img, side, sky0, mo[0], mo[1], mo + 2, kind, w0, tol, max_iter, os, &its,
-                     &sst);
+    orc_star_moments(img, side, sky0, mo[0], mo[1], mo + 2, kind, beta_fixed, w0, tol, max_iter,
+                     os, &its, &sst);
     iters[s] = its;
     status[s] = sst;
   }

@@ -32,6 +32,7 @@ extern "C" {
 
 #define ORC_SERSIC 0
 #define ORC_MOFFAT 1
+#define ORC_MOFFAT_BETA 2   /* star estimator only: Moffat with beta fixed */
 
 typedef struct {
   int      max_iter_centroid;  /* cap on centroid steps (Sec. 4.1: 20) */
@@ -108,11 +109,12 @@ void orc_fit(const double* img, int side, double sigma, int kind, const double* 
              uint32_t* status, double* perr);
 
 /* Star size from weighted moments (Sec. 4.2): kind ORC_SERSIC = Gaussian star,
- * ORC_MOFFAT = Moffat star; w0 = starting weight width; out[6] =
+ * ORC_MOFFAT = Moffat star, ORC_MOFFAT_BETA = Moffat star with beta fixed at
+ * beta_fixed (ignored otherwise); w0 = starting weight width; out[6] =
  * (sigma or rd, beta, I0, r0, r2, r4). */
 void orc_star_moments(const double* img, int side, double sky, double xc, double yc,
-                      const double* g, int kind, double w0, double tol, int max_iter,
-                      double* out, int* iters, uint32_t* status);
+                      const double* g, int kind, double beta_fixed, double w0, double tol,
+                      int max_iter, double* out, int* iters, uint32_t* status);
 
 /* Whole pipeline over a batch, OpenMP over stamps.  Returns threads used.
  * pixels: FP64 packed stamps; offsets/sides/sigma/model per stamp.
@@ -135,10 +137,11 @@ void orc_frame_detect(const double* img, int H, int W, int max_side, double* sky
 
 /* Star sizes over a batch (Sec. 4.2), OpenMP over stamps; returns threads
  * used.  Per stamp: starting estimates, centroid, joint centre + ellipticity,
- * then orc_star_moments of the given kind; out[6] as there, iters, status. */
+ * then orc_star_moments of the given kind (beta_fixed for ORC_MOFFAT_BETA);
+ * out[6] as there, iters, status. */
 int orc_star_pipeline(int64_t n, const double* pixels, const int64_t* offsets,
-                      const int32_t* sides, const orc_opts* o, int kind, double tol,
-                      int max_iter, double* out, int32_t* iters, uint32_t* status,
+                      const int32_t* sides, const orc_opts* o, int kind, double beta_fixed,
+                      double tol, int max_iter, double* out, int32_t* iters, uint32_t* status,
                       int threads);
 
 #ifdef __cplusplus

@@ -126,6 +126,9 @@ def _load():
     lib.shape_chi2_bwd.restype = C.c_int
     lib.shape_star_moments.argtypes = [bp, C.c_int32, vp, C.c_double, C.c_int32, vp, vp, vp, vp]
     lib.shape_star_moments.restype = C.c_int
+    lib.shape_star_moments_beta.argtypes = [bp, C.c_double, vp, C.c_double, C.c_int32, vp, vp, vp,
+                                            vp]
+    lib.shape_star_moments_beta.restype = C.c_int
     fp = C.POINTER(ShapeFrames)
     lib.shape_frame_detect.argtypes = [fp, C.c_int32, vp, vp, vp, vp, vp]
     lib.shape_frame_offsets.argtypes = [vp, C.c_int64, vp, vp, vp]
@@ -472,6 +475,20 @@ def star_moments(batch: DeviceBatch, rec: torch.Tensor, profile: int = STAR_GAUS
     _check(lib.shape_star_moments(C.byref(b), int(profile), _ptr(rec), float(tol), int(max_iter),
                                   _ptr(out), _ptr(it), _ptr(st), _stream(dev)),
            "shape_star_moments")
+    return out, it, st
+
+
+def star_moments_beta(batch: DeviceBatch, rec: torch.Tensor, beta: float, tol: float = 1e-4,
+                      max_iter: int = 20):
+    """shape_star_moments_beta (Moffat, beta fixed): returns (out [n,4] = rd,
+    beta, I0, r0; iters; status)."""
+    n, dev = batch.n, batch.device
+    rec = _rows(rec, n, REC_LEN, "rec", dev)
+    out, it, st = _outs(n, dev, ((n, 4), torch.float32), ((n,), torch.int32), ((n,), torch.int32))
+    b = batch.c_struct()
+    _check(lib.shape_star_moments_beta(C.byref(b), float(beta), _ptr(rec), float(tol),
+                                       int(max_iter), _ptr(out), _ptr(it), _ptr(st),
+                                       _stream(dev)), "shape_star_moments_beta")
     return out, it, st
 
 

@@ -182,7 +182,19 @@ int shape_star_moments(const shape_batch* b, int32_t profile, const float* rec, 
   if (b->n == 0) return SHAPE_OK;
   if (!rec || !out || !iters || !status) return SHAPE_EINVAL;
   return from_hip(
-      launch_stars(*b, profile, rec, tol, max_iter, out, iters, status, (hipStream_t)stream));
+      launch_stars(*b, profile, rec, tol, max_iter, 3.0, out, iters, status, (hipStream_t)stream));
+}
+
+int shape_star_moments_beta(const shape_batch* b, double beta, const float* rec, double tol,
+                            int32_t max_iter, float* out, int32_t* iters, uint32_t* status,
+                            void* stream) {
+  int rc = check_batch(b);
+  if (rc != SHAPE_OK) return rc;
+  if (!(beta > 1.0 && beta <= 1e6) || !(tol >= 0.0) || max_iter < 0) return SHAPE_EINVAL;
+  if (b->n == 0) return SHAPE_OK;
+  if (!rec || !out || !iters || !status) return SHAPE_EINVAL;
+  return from_hip(
+      launch_stars(*b, 2, rec, tol, max_iter, beta, out, iters, status, (hipStream_t)stream));
 }
 
 static int check_frames(const shape_frames* f) {

@@ -60,7 +60,7 @@ hipError_t launch_fit_queue_static(const shape_batch& b, const KOpts& o, const f
                                    int32_t* sweeps, hipStream_t stream);
 
 hipError_t launch_stars(const shape_batch& b, int profile, const float* rec, double tol,
-                        int max_iter, float* out, int32_t* iters, uint32_t* status,
+                        int max_iter, double beta, float* out, int32_t* iters, uint32_t* status,
                         hipStream_t stream);
 
 int frame_bins(int height, int width);

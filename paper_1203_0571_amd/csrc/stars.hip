@@ -9,12 +9,17 @@
 //   Moffat   (Sec. 4.2.2, W = (1 + R^2 / w^2)^-3): beta = 1 / (r4 r0 / 2 r2^2 - 1),
 //            rd = sqrt(r2 / r0 (beta + 1)), I0 = r0 (beta + 2) / (pi rd^2)
 //            (exact when w = rd);
+//   Moffat with beta fixed (the paper's way out of the rd-beta degeneracy:
+//            beta from bright stars, fixed for fainter ones): the same weight,
+//            rd and I0 from r0 and r2 with the given beta (r4 unused);
 // and sets w to the new size until the fractional change is below tol.
 //
 // Only w changes from step to step, so f and R^2 of every pixel are formed
-// once.  Stamps of up to 64 x kCache pixels keep them in registers (pixel
-// lane + 64 q in slot q) and read HBM once; larger stamps recompute them from
-// the stamp on every step.
+// once.  One wave per stamp: stamps of up to 64 x kCache pixels keep f and
+// R^2 in registers (pixel lane + 64 q in slot q) and read HBM once; larger
+// stamps recompute them from the stamp on every step.  (Two 32 x 32 stamps per
+// wave, each on a half-wave, ran slower: a wave then iterates as long as the
+// slower of its two stars.)
 #include "kernels.hpp"
 
 namespace shape {
@@ -53,10 +58,57 @@ __device__ __forceinline__ void star_accumulate(float f, float R2, float c, floa
 // Pixels a lane sums in FP32 before carrying the partial sums on in FP64.
 constexpr int kStarBlock = 8;
 
+// Profiles: 0 Gaussian, 1 Moffat, 2 Moffat with beta fixed.
+__host__ __device__ constexpr bool moffat_weight(int profile) { return profile != 0; }
+
+// The weight's constant for width w (w > 0).
+template <int PROFILE>
+__device__ __forceinline__ float weight_const(double w) {
+  const double iw2 = rcp_f64(w * w);
+  return (float)(moffat_weight(PROFILE) ? iw2 : 0.5 * kLog2e * iw2);
+}
+
+// The starting width: the Gaussian's sigma_w, or the Moffat (beta = 3, or
+// the fixed beta) whose half-light radius is r50: its enclosed flux is
+// 1 - (1 + R^2 / rd^2)^(1 - beta) of the total.
+template <int PROFILE>
+__device__ __forceinline__ double start_width(const float (&r)[SHAPE_REC_LEN], double beta_fixed) {
+  if constexpr (PROFILE == 0) return (double)r[SHAPE_REC_SIGW];
+  const double bw = PROFILE == 2 ? beta_fixed : 3.0;
+  return (double)r[SHAPE_REC_R50] / sqrt(exp2(1.0 / (bw - 1.0)) - 1.0);
+}
+
+// One step from the sums (s0, s2, s4) = (r0, r2, r4): the new size, and beta
+// for the free Moffat; false when the step cannot be taken (status in stt).
+template <int PROFILE>
+__device__ __forceinline__ bool star_step(double s0, double s2, double s4, double& beta,
+                                          double& ns, uint32_t& stt) {
+  if (!(s0 > 0.0) || !(s2 > 0.0)) {
+    stt |= SHAPE_ST_NONPOSITIVE_FLUX;
+    return false;
+  }
+  const double is0 = rcp_f64(s0);   // s0, s2 > 0 here; reciprocals by Newton
+  if constexpr (PROFILE == 0) {
+    ns = sqrt(s2 * is0);
+  } else {
+    if constexpr (PROFILE == 1) {
+      const double is2 = rcp_f64(s2);
+      const double q = 0.5 * s4 * s0 * is2 * is2 - 1.0;
+      if (!(q > 0.0)) {
+        stt |= SHAPE_ST_SINGULAR;
+        return false;
+      }
+      beta = rcp_f64(q);
+    }
+    ns = sqrt(s2 * is0 * (beta + 1.0));
+  }
+  return true;
+}
+
 template <int DT, int PROFILE>
 __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float* rec, double tol,
-                                                     int max_iter, float* out, int32_t* iters,
-                                                     uint32_t* status) {
+                                                     int max_iter, double beta_fixed, float* out,
+                                                     int32_t* iters, uint32_t* status) {
   const int lane = threadIdx.x;
   for (int64_t s = blockIdx.x; s < b.n; s += gridDim.x) {
     const Stamp st = stamp_info(b, s);
@@ -99,16 +151,12 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
         }
       }
     }
-    // starting width: the Gaussian of half-light radius r50, or the beta = 3
-    // Moffat of that half-light radius (r50 = rd sqrt(2^(1/2) - 1))
-    double w = PROFILE == 0 ? (double)r[SHAPE_REC_SIGW]
-                            : (double)r[SHAPE_REC_R50] / sqrt(sqrt(2.0) - 1.0);
-    double size = w, beta = 0.0, I0 = 0.0, r0 = 0.0, s0_ok = 0.0;
+    double w = start_width<PROFILE>(r, beta_fixed);
+    double size = w, beta = PROFILE == 2 ? beta_fixed : 0.0, I0 = 0.0, r0 = 0.0, s0_ok = 0.0;
     uint32_t stt = 0;
     int it = 0;
     while (it < max_iter) {
-      const double iw2 = rcp_f64(w * w);   // w > 0: the start and every new size
-      const float c = (float)(PROFILE == 0 ? 0.5 * kLog2e * iw2 : iw2);
+      const float c = weight_const<PROFILE>(w);   // w > 0: the start and every new size
       double u[4] = {0.0, 0.0, 0.0, 0.0};   // r0, r2, r4 (and a pad)
       float sp[3] = {0.0f, 0.0f, 0.0f};
       auto carry = [&]() {
@@ -140,25 +188,8 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
       const double s0 = u[0], s2 = u[1], s4 = u[2];
       ++it;
       r0 = s0;
-      if (!(s0 > 0.0) || !(s2 > 0.0)) {
-        stt |= SHAPE_ST_NONPOSITIVE_FLUX;
-        break;
-      }
-      // (s0, s2 > 0 here; reciprocals by Newton, I0 once after the loop)
-      const double is0 = rcp_f64(s0);
       double ns;
-      if constexpr (PROFILE == 0) {
-        ns = sqrt(s2 * is0);
-      } else {
-        const double is2 = rcp_f64(s2);
-        const double q = 0.5 * s4 * s0 * is2 * is2 - 1.0;
-        if (!(q > 0.0)) {
-          stt |= SHAPE_ST_SINGULAR;
-          break;
-        }
-        beta = rcp_f64(q);
-        ns = sqrt(s2 * is0 * (beta + 1.0));
-      }
+      if (!star_step<PROFILE>(s0, s2, s4, beta, ns, stt)) break;
       const bool small = fabs(ns - w) < tol * ns;   // fractional change below tol
       size = ns;
       w = ns;
@@ -184,29 +215,34 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
 }
 
 template <int DT, int PROFILE>
-void launch_one(const shape_batch& b, const float* rec, double tol, int max_iter, float* out,
-                int32_t* iters, uint32_t* status, hipStream_t stream) {
-  const int64_t grid = b.n < (1ll << 30) ? b.n : (1ll << 30);
+void launch_one(const shape_batch& b, const float* rec, double tol, int max_iter, double beta,
+                float* out, int32_t* iters, uint32_t* status, hipStream_t stream) {
+  const int64_t cap = 1ll << 30;
+  const int64_t grid = b.n < cap ? b.n : cap;
   hipLaunchKernelGGL((star_kernel<DT, PROFILE>), dim3((unsigned)grid), dim3(kWave), 0, stream, b,
-                     rec, tol, max_iter, out, iters, status);
+                     rec, tol, max_iter, beta, out, iters, status);
+}
+
+template <int DT>
+void launch_dtype(const shape_batch& b, int profile, const float* rec, double tol, int max_iter,
+                  double beta, float* out, int32_t* iters, uint32_t* status, hipStream_t stream) {
+  switch (profile) {
+    case 0: launch_one<DT, 0>(b, rec, tol, max_iter, beta, out, iters, status, stream); break;
+    case 1: launch_one<DT, 1>(b, rec, tol, max_iter, beta, out, iters, status, stream); break;
+    default: launch_one<DT, 2>(b, rec, tol, max_iter, beta, out, iters, status, stream);
+  }
 }
 
 }  // namespace
 
 hipError_t launch_stars(const shape_batch& b, int profile, const float* rec, double tol,
-                        int max_iter, float* out, int32_t* iters, uint32_t* status,
+                        int max_iter, double beta, float* out, int32_t* iters, uint32_t* status,
                         hipStream_t stream) {
-  if (b.dtype == SHAPE_F32) {
-    if (profile == 0)
-      launch_one<SHAPE_F32, 0>(b, rec, tol, max_iter, out, iters, status, stream);
-    else
-      launch_one<SHAPE_F32, 1>(b, rec, tol, max_iter, out, iters, status, stream);
-  } else {
-    if (profile == 0)
-      launch_one<SHAPE_F16_SCALED, 0>(b, rec, tol, max_iter, out, iters, status, stream);
-    else
-      launch_one<SHAPE_F16_SCALED, 1>(b, rec, tol, max_iter, out, iters, status, stream);
-  }
+  if (b.dtype == SHAPE_F32)
+    launch_dtype<SHAPE_F32>(b, profile, rec, tol, max_iter, beta, out, iters, status, stream);
+  else
+    launch_dtype<SHAPE_F16_SCALED>(b, profile, rec, tol, max_iter, beta, out, iters, status,
+                                   stream);
   return hipGetLastError();
 }
 

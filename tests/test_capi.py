@@ -204,6 +204,14 @@ def test_star_moments_argument_errors(shape):
     assert L.shape_star_moments(None, 1, out, 1e-4, 20, out, out, out, None) == shape.EINVAL
     e = _batch(shape, n=0, pixels=None, sigma=None)
     assert L.shape_star_moments(C.byref(e), 0, None, 1e-4, 20, None, None, None, None) == shape.OK
+    Lb = L.shape_star_moments_beta
+    for beta in (1.0, 0.5, -3.0, float("nan"), 2e6):
+        assert Lb(C.byref(b), beta, out, 1e-4, 20, out, out, out, None) == shape.EINVAL
+    assert Lb(C.byref(b), 3.0, out, -1.0, 20, out, out, out, None) == shape.EINVAL
+    assert Lb(C.byref(b), 3.0, out, 1e-4, -1, out, out, out, None) == shape.EINVAL
+    assert Lb(C.byref(b), 3.0, None, 1e-4, 20, out, out, out, None) == shape.EINVAL
+    assert Lb(None, 3.0, out, 1e-4, 20, out, out, out, None) == shape.EINVAL
+    assert Lb(C.byref(e), 3.0, None, 1e-4, 20, None, None, None, None) == shape.OK
 
 
 def _frames(shape, **kw):

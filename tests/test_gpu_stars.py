@@ -17,33 +17,41 @@ pytestmark = pytest.mark.gpu
 BAR_REL = 1e-3
 
 
+BETA_FIXED = 3.75   # the workload's mean beta (U(2.5, 5))
+
+
 def _oracle_chain(batch, profile, tol, max_iter, o):
-    kind = oracle.SERSIC if profile == 0 else oracle.MOFFAT
-    r = oracle.star_pipeline(batch, kind, tol, max_iter, o)
+    kind = (oracle.SERSIC, oracle.MOFFAT, oracle.MOFFAT_BETA)[profile]
+    r = oracle.star_pipeline(batch, kind, tol, max_iter, o, beta=BETA_FIXED)
     return r["out"][:, :4], r["iters"], r["status"]
 
 
-def _gpu_chain(batch, profile, tol, max_iter):
+def _gpu_chain(batch, profile, tol, max_iter, uniform=None):
     import torch
     import paper_1203_0571_amd as shape
-    db = shape.DeviceBatch.from_host(batch, "cuda:0")
+    db = shape.DeviceBatch.from_host(batch, "cuda:0", uniform=uniform)
     rec0, _, _ = shape.centroid(db)
     rec1, _, _ = shape.moments(db, rec0)
-    out, it, st = shape.star_moments(db, rec1, profile, tol, max_iter)
+    if profile == 2:
+        out, it, st = shape.star_moments_beta(db, rec1, BETA_FIXED, tol, max_iter)
+    else:
+        out, it, st = shape.star_moments(db, rec1, profile, tol, max_iter)
     torch.cuda.synchronize()
     return out.cpu().numpy().astype(np.float64), it.cpu().numpy(), \
         st.cpu().numpy().astype(np.uint32)
 
 
-@pytest.mark.parametrize("workload,profile,tol,max_iter", [
-    ("plain32", 0, 1e-4, 20),     # the paper's stopping rule
-    ("plain32", 0, 1e-7, 200),
-    ("stars32", 1, 1e-4, 20),
-    ("stars32", 1, 1e-7, 200),
+@pytest.mark.parametrize("workload,profile,tol,max_iter,n", [
+    ("plain32", 0, 1e-4, 20, 256),     # the paper's stopping rule
+    ("plain32", 0, 1e-7, 200, 256),
+    ("stars32", 1, 1e-4, 20, 256),
+    ("stars32", 1, 1e-7, 200, 255),
+    ("stars32", 2, 1e-4, 20, 256),     # beta fixed
+    ("stars32", 2, 1e-7, 200, 255),
 ])
-def test_star_moments_vs_oracle(workload, profile, tol, max_iter):
+def test_star_moments_vs_oracle(workload, profile, tol, max_iter, n):
     import paper_1203_0571_amd as shape
-    batch = synth.make(workload, 256)
+    batch = synth.make(workload, n)
     o = oracle_opts_like(shape.default_opts())
     ref, it_o, st_o = _oracle_chain(batch, profile, tol, max_iter, o)
     got, it_g, st_g = _gpu_chain(batch, profile, tol, max_iter)
@@ -59,6 +67,9 @@ def test_star_moments_vs_oracle(workload, profile, tol, max_iter):
     assert rel.max() <= BAR_REL
     if profile == 0:
         assert np.all(got[:, 1] == 0.0)
+    if profile == 2:
+        assert np.all(got[:, 1] == np.float32(BETA_FIXED))
+        assert both.mean() >= 0.95   # no fourth moment, no singular step
 
 
 def test_star_moments_edge_cases():

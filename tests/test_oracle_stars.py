@@ -91,7 +91,50 @@ def test_moffat_inversion_exact_at_matched_weight():
     assert r["size"] == pytest.approx(rd, rel=1e-4)
 
 
-@pytest.mark.parametrize("kind", [oracle.SERSIC, oracle.MOFFAT])
+def test_moffat_fixed_beta_inversion_exact_at_matched_weight():
+    """Beta fixed at the star's own: the pixel sums at rdw = rd give rd and I0
+    through r0 and r2 alone (eqs. mofrditer, mofI0iter with beta known)."""
+    side = 128
+    c = (63.5, 63.5)
+    beta, rd = 4.0, 4.0
+    img = synth.render_moffat(side, np.array([c[0], c[1], 0, 0, rd, beta, 1000.0, 0]))[0]
+    r = oracle.star_moments(img, 0.0, c[0], c[1], (0.0, 0.0), oracle.MOFFAT_BETA, rd, max_iter=1,
+                            beta=beta)
+    assert r["beta"] == beta
+    assert r["size"] == pytest.approx(rd, rel=1e-5)
+    assert r["I0"] == pytest.approx(1000.0, rel=1e-5)
+
+
+def test_moffat_fixed_beta_iteration_recovers_rd():
+    """From a weight twice too wide, the fixed-beta iteration converges to the
+    star's rd; with a wrong beta it converges to a different width."""
+    side = 128
+    c = (64.4, 63.7)
+    p = np.array([c[0], c[1], 0.0, 0.0, 5.0, 3.5, 400.0, 0.0])
+    img = synth.render_moffat(side, p)[0]
+    r = oracle.star_moments(img, 0.0, c[0], c[1], (0.0, 0.0), oracle.MOFFAT_BETA, 10.0, tol=1e-12,
+                            max_iter=200, beta=3.5)
+    assert r["status"] & oracle.CONVERGED
+    assert r["size"] == pytest.approx(5.0, rel=1e-4)
+    assert r["I0"] == pytest.approx(400.0, rel=1e-4)
+    w = oracle.star_moments(img, 0.0, c[0], c[1], (0.0, 0.0), oracle.MOFFAT_BETA, 10.0, tol=1e-12,
+                            max_iter=200, beta=5.0)
+    assert w["status"] & oracle.CONVERGED and abs(w["size"] / 5.0 - 1) > 0.05
+
+
+def test_moffat_fixed_beta_converges_where_free_beta_does_not():
+    """On the 32^2 star workload (beta U(2.5, 5)) a noisy fourth moment often
+    makes the free-beta estimate undefined (r4 r0 / (2 r2^2) <= 1); with beta
+    fixed (the paper's remedy, Sec. 4.2.2) r4 is not needed."""
+    b = synth.make("stars32", 512)
+    free = oracle.star_pipeline(b, oracle.MOFFAT, 1e-4, 20)
+    fixed = oracle.star_pipeline(b, oracle.MOFFAT_BETA, 1e-4, 20, beta=3.75)
+    conv = lambda r: ((r["status"] & oracle.CONVERGED) != 0).mean()
+    assert conv(free) < 0.8
+    assert conv(fixed) > 0.97
+
+
+@pytest.mark.parametrize("kind", [oracle.SERSIC, oracle.MOFFAT, oracle.MOFFAT_BETA])
 def test_batched_chain_matches_per_stamp_calls(kind):
     """orc_star_pipeline is the per-stamp chain init -> centroid -> moments ->
     star estimator, run over a batch."""
@@ -104,6 +147,7 @@ def test_batched_chain_matches_per_stamp_calls(kind):
         x, y, _, _ = oracle.centroid(img, ini["sky0"], ini["sigw"], ini["imax"] % 32,
                                      ini["imax"] // 32, o)
         mo, _, _ = oracle.moments(img, ini["sky0"], ini["sigw"], ini["r50"], x, y, o)
+        # the Moffat of half-light radius r50 with beta = 3 (also the fixed beta here)
         w0 = ini["sigw"] if kind == oracle.SERSIC else ini["r50"] / math.sqrt(math.sqrt(2) - 1)
         s = oracle.star_moments(img, ini["sky0"], mo[0], mo[1], mo[2:4], kind, w0)
         assert s["status"] == r["status"][i]

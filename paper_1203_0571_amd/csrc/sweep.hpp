@@ -31,13 +31,14 @@ __host__ __device__ inline constexpr int nth_bit(uint32_t m, int a) {
   return 0;
 }
 
-// FP64 log2 and exp2 for the FP64 instance of the sweep, from series.
+// FP64 log2 and exp2 from series alone, accurate to about 1e-17 relative:
 //   log2 x: x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh z,
 //           z = (m - 1)/(m + 1), |z| <= 3 - 2 sqrt(2); the odd series to z^23
 //           leaves a relative error below 1e-19.
 //   exp2 x: x = k + f with k = rint(x), |f| <= 1/2; e^(f ln 2) by its Taylor
 //           series to degree 13 (remainder below 1e-17), scaled by 2^k.
-__device__ __forceinline__ double log2_f64(double x) {
+// They fill the tables of the per-pixel forms below.
+__device__ __forceinline__ double log2_series(double x) {
   int e;
   double m = __builtin_frexp(x, &e);  // [0.5, 1)
   if (m < 0.70710678118654752) {
@@ -52,7 +53,7 @@ __device__ __forceinline__ double log2_f64(double x) {
   return (double)e + 2.0 * z * s * kLog2e;
 }
 
-// 1 / n! for the Taylor series of e^y, as compile-time constants.
+// 1 / n! for Taylor series of e^y, as compile-time constants.
 template <int N>
 struct InvFact {
   static constexpr double v = InvFact<N - 1>::v / N;
@@ -61,21 +62,70 @@ template <>
 struct InvFact<0> {
   static constexpr double v = 1.0;
 };
-// sum_{n = M..13} y^(n-M) / n! by Horner (M = 0: the series of e^y).
-template <int M>
+// sum_{n = M..D} y^(n-M) / n! by Horner (M = 0: the series of e^y to degree D).
+template <int D, int M = 0>
 __device__ __forceinline__ double exp_taylor(double y) {
-  if constexpr (M == 13)
-    return InvFact<13>::v;
+  if constexpr (M == D)
+    return InvFact<D>::v;
   else
-    return fma(exp_taylor<M + 1>(y), y, InvFact<M>::v);
+    return fma(exp_taylor<D, M + 1>(y), y, InvFact<M>::v);
+}
+
+__device__ __forceinline__ double exp2_series(double x) {
+  if (!(x > -1100.0)) return x != x ? x : 0.0;
+  if (x > 1100.0) return __builtin_inf();
+  const double k = __builtin_rint(x);
+  const double y = (x - k) * kLn2;
+  return __builtin_ldexp(exp_taylor<13>(y), (int)k);
+}
+
+// Per-pixel FP64 log2 and exp2 of the FP64 instance (Tang's table method):
+// the argument is reduced against 64 table points, and a short series covers
+// the remainder, cut where its error is below 4e-14 relative -- some 1e5
+// times below what the gradient's bar needs (the FP32 instance, at ~1e-7,
+// misses it by ~1e3; the largest gradient error against the oracle, about
+// 1e-7 of the largest component, is the same as with the series cut at
+// 1e-17).
+//   log2 x: x = 2^e m2, m2 in [1, 2); j = the top 6 bits of m2's fraction,
+//           c_j = 1 + (j + 1/2) / 64, r = m2 / c_j - 1 (|r| < 1/128);
+//           log2 x = e + log2 c_j + ln(1 + r) log2 e, ln(1 + r) to r^5
+//           (the first dropped term, r^6 / 6, is below 4e-14).
+//   exp2 x: x = (64 k + j) / 64 + f, |f| <= 1/128; 2^x = 2^k 2^(j/64) e^(f ln 2),
+//           the Taylor series of e^y to degree 4 (remainder below 4e-14).
+// The tables (2^(j/64), 1 / c_j, log2 c_j) live in LDS; f64_tables_fill
+// forms them with the series above, before the first sweep of a kernel.
+constexpr int kF64Tab = 64;
+__shared__ double f64_tab[3 * kF64Tab];
+
+__device__ __forceinline__ void f64_tables_fill(int t, int nthreads) {
+  for (int j = t; j < kF64Tab; j += nthreads) {
+    const double c = 1.0 + (j + 0.5) / kF64Tab;
+    f64_tab[j] = exp2_series(j / (double)kF64Tab);
+    f64_tab[kF64Tab + j] = 1.0 / c;
+    f64_tab[2 * kF64Tab + j] = log2_series(c);
+  }
+}
+
+__device__ __forceinline__ double log2_f64(double x) {   // x > 0, finite
+  int e;
+  const double m = __builtin_frexp(x, &e);   // [0.5, 1), the same fraction bits
+  const uint32_t hi = (uint32_t)(__builtin_bit_cast(uint64_t, m) >> 32);
+  const int j = (int)((hi >> 14) & (kF64Tab - 1));   // top 6 of the 52 fraction bits
+  const double r = fma(2.0 * m, f64_tab[kF64Tab + j], -1.0);
+  double s = 1.0 / 5.0;   // ln(1 + r) = r (1 - r/2 + r^2/3 - r^3/4 + r^4/5)
+#pragma unroll
+  for (int k = 4; k >= 1; --k) s = fma(s, r, ((k & 1) ? 1.0 : -1.0) / (double)k);
+  return fma(r * s, kLog2e, (double)(e - 1) + f64_tab[2 * kF64Tab + j]);
 }
 
 __device__ __forceinline__ double exp2_f64(double x) {
   if (!(x > -1100.0)) return x != x ? x : 0.0;
   if (x > 1100.0) return __builtin_inf();
-  const double k = __builtin_rint(x);
-  const double y = (x - k) * kLn2;
-  return __builtin_ldexp(exp_taylor<0>(y), (int)k);
+  const double K = __builtin_rint(x * kF64Tab);
+  const int ki = (int)K;
+  const int j = ki & (kF64Tab - 1), k = ki >> 6;   // floor division by 64
+  const double y = fma(K, -1.0 / kF64Tab, x) * kLn2;   // |y| <= ln 2 / 128
+  return __builtin_ldexp(f64_tab[j] * exp_taylor<4>(y), k);
 }
 
 // Arithmetic of one sweep instance: FP32 with the hardware transcendentals
@@ -97,9 +147,14 @@ template <>
 struct Arith<double> {
   static __device__ __forceinline__ double ex2(double x) { return exp2_f64(x); }
   static __device__ __forceinline__ double lg2(double x) { return log2_f64(x); }
-  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double rcp(double x) { return rcp_f64(x); }
   static __device__ __forceinline__ double fma(double a, double b, double c) { return ::fma(a, b, c); }
-  static __device__ __forceinline__ double uni(double v) { return v; }
+  static __device__ __forceinline__ double uni(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  }
   static constexpr double kR2Floor = 1e-8;
 };
 
@@ -237,8 +292,10 @@ __host__ __device__ inline constexpr bool rows_layout_fits(int side) {
 #define SHAPE_SWEEP_FLUSH 8
 #endif
 
+// JTJ = false leaves the J^T J sums at zero (callers that need only chi^2
+// and J^T r).
 template <int DT, int MODEL, uint32_t EM, int STRIDE = kWave, typename T = float,
-          int LAYOUT = kLayoutAny>
+          int LAYOUT = kLayoutAny, bool JTJ = true>
 __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, const Trial<T>& t,
                              Acc<EM, T>& acc, int tid = -1, void* stage = nullptr) {
   using A = Arith<T>;
@@ -319,14 +376,16 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
         gp[a] = (a == 7) ? gp[a] + r : A::fma(J[a], r, gp[a]);
       else
         acc.g[a] = (a == 7) ? acc.g[a] + rd : fma((double)J[a], rd, acc.g[a]);
+      if constexpr (JTJ) {
 #pragma unroll
-      for (int c = a; c < 8; ++c) {
-        if (!has(EM, c)) continue;
-        if (c == 7 && a == 7) continue;   // the count of pixels, set by the caller
-        if (c == 7)
-          acc.A[tri(a, c)] += J[a];
-        else
-          acc.A[tri(a, c)] = A::fma(J[a], J[c], acc.A[tri(a, c)]);
+        for (int c = a; c < 8; ++c) {
+          if (!has(EM, c)) continue;
+          if (c == 7 && a == 7) continue;   // the count of pixels, set by the caller
+          if (c == 7)
+            acc.A[tri(a, c)] += J[a];
+          else
+            acc.A[tri(a, c)] = A::fma(J[a], J[c], acc.A[tri(a, c)]);
+        }
       }
     }
   };

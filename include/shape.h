@@ -283,8 +283,10 @@ int shape_star_moments_beta(const shape_batch* batch, double beta, const float* 
 typedef struct {
   int32_t team;           /* waves per stamp for stamps with side >= team_min_side: 1, 2, 4 */
   int32_t team_min_side;  /* threshold side for team processing (team > 1) */
-  int32_t grid;           /* persistent workgroups; 0 = as many as fit on the device;
-                             1 .. 7 are raised to 8 (one per cursor) */
+  int32_t grid;           /* persistent workgroups of the sweep kernels; 0 = as many
+                             as fit on the device (any count >= 1 drains every stamp:
+                             a workgroup moves on to the next cursor when its own is
+                             drained) */
   int32_t reserved;
 } shape_queue_cfg;
 

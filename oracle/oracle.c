@@ -47,7 +47,12 @@ void orc_default_opts(orc_opts* o) {
 /* ------------------------------------------------------------------------ */
 
 /* P(a, x) from its power series (x < a + 1) or from the continued fraction
- * of Q(a, x) = 1 - P(a, x) (otherwise). */
+ * of Q(a, x) = 1 - P(a, x) (otherwise), the standard pair for the regularised
+ * incomplete gamma function (e.g. Press et al., Numerical Recipes, 3rd ed.,
+ * Sec. 6.2).  The continued fraction is evaluated by the modified Lentz
+ * method (W. J. Lentz, Appl. Opt. 15, 668 (1976); I. J. Thompson and
+ * A. R. Barnett, J. Comput. Phys. 64, 490 (1986)), whose steps and names
+ * (a_n, b_n, C, D, the product h and its factor del) this follows. */
 double orc_gamma_p(double a, double x) {
   if (x <= 0.0) return 0.0;
   double lpre = a * log(x) - x - lgamma(a);

@@ -410,7 +410,7 @@ def main():
     if cpu:
         line["cpu_baseline"] = cpu
     if tuned:
-        line["config"]["queue_cfg"] = {f: dict(team=t["cfg"].team, team_min_side=t["cfg"].team_min_side,
+        line["config"]["queue_cfg"] = {f: dict(team=t["cfg"].team, team_min_side=t["cfg"].team_min_side, chunk=t["cfg"].chunk,
                                                grid=t["cfg"].grid, drain_frac=t["drain_frac"])
                                        for f, t in tuned.items()}
     # context, not the target: the paper's single-core timings for this path
@@ -455,7 +455,7 @@ def bench_uneven(args):
         t = time.time()
         tuned = autotune.tune_queue(db, rec1, opts, use_cache=False)
         cfg, drain_at = tuned["cfg"], int(tuned["drain_frac"] * db.n)
-        log("autotune %.1f s: best %s drain %.2f" % (time.time() - t, dict(team=cfg.team, team_min_side=cfg.team_min_side, grid=cfg.grid), tuned["drain_frac"]))
+        log("autotune %.1f s: best %s drain %.2f" % (time.time() - t, dict(team=cfg.team, team_min_side=cfg.team_min_side, grid=cfg.grid, chunk=cfg.chunk), tuned["drain_frac"]))
 
     def step(form, ev=None):
         if ev:
@@ -506,7 +506,8 @@ def bench_uneven(args):
             "data": "synthetic",
             "config": {"workload": "uneven: %d stamps, seed 0" % b.n, "chosen_form": best,
                        "queue_cfg": (dict(team=cfg.team, team_min_side=cfg.team_min_side,
-                                          grid=cfg.grid) if cfg else None),
+                                          grid=cfg.grid, chunk=cfg.chunk,
+                                          drain_frac=tuned["drain_frac"]) if cfg else None),
                        "forms": {f: {k: round(v, 4) for k, v in x.items()} for f, x in res.items()}},
             "roofline": {"bound": "alu", "kernel": "fit (" + best + ")",
                          "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS,

@@ -287,10 +287,12 @@ typedef struct {
                              as fit on the device (any count >= 1 drains every stamp:
                              a workgroup moves on to the next cursor when its own is
                              drained) */
-  int32_t reserved;
+  int32_t chunk;          /* stamps a wave (or team) takes from a cursor at most per
+                             pop, 1 .. 64; 0 = 8.  Pops shrink towards one stamp as a
+                             cursor's share runs out */
 } shape_queue_cfg;
 
-/* Defaults: team 1 (one wave per stamp), grid 0. */
+/* Defaults: team 1 (one wave per stamp), grid 0, chunk 0. */
 int shape_queue_default_cfg(shape_queue_cfg* cfg);
 /* Workspace bytes for n stamps (about 1.05 KB per stamp). */
 int shape_queue_workspace_bytes(int64_t n, size_t* bytes);

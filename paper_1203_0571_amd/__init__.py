@@ -87,7 +87,7 @@ class QueueCfg(C.Structure):
         ("team", C.c_int32),
         ("team_min_side", C.c_int32),
         ("grid", C.c_int32),
-        ("reserved", C.c_int32),
+        ("chunk", C.c_int32),
     ]
 
 

@@ -1,14 +1,18 @@
 """Autotuner for the work-queue fit: waves per stamp, team threshold,
-persistent grid and the point where the drain pass takes over.
+persistent grid, stamps per cursor pop and the point where the drain pass
+takes over.
 
 For a batch it times the whole queue fit (start, graph-replayed steps, drain,
-finish) for each candidate on an evenly spaced sample of the batch: teams of
-1, 2 or 4 waves for stamps at or above a threshold side; the persistent grid
-at the resident workgroup count or half of it; the drain once the active
-stamps fall to 2%, 8% or 25% of the batch.  It keeps the fastest and caches
-the choice in a JSON file keyed by the device, the free mask, the storage
-type and a coarse histogram of the stamp sides.  The cache lives in
-$SHAPE_TUNE_CACHE (default ~/.cache/shape/queue_tune.json).
+finish) for each candidate on an evenly spaced sample of the batch.  First
+round: teams of 1, 2 or 4 waves for stamps at or above a threshold side; the
+persistent grid at the resident workgroup count or half of it; the drain once
+the active stamps fall to 2%, 8% or 25% of the batch (chunk 8).  Second
+round: the best of those with 2, 4, 16 or 32 stamps per pop.  It keeps the
+fastest and caches the choice in a JSON file keyed by the device, the free
+mask, the storage type and a coarse histogram of the stamp sides.  The cache
+lives in $SHAPE_TUNE_CACHE (default ~/.cache/shape/queue_tune.json).
+(Waves per SIMD are fixed when the kernels are compiled: four, as the fused
+fit, where the sweep's registers fit without spills.)
 """
 from __future__ import annotations
 
@@ -24,6 +28,7 @@ TEAMS = [dict(team=1, team_min_side=96), dict(team=2, team_min_side=64),
          dict(team=2, team_min_side=96), dict(team=4, team_min_side=96)]
 GRID_FRACTIONS = [1.0, 0.5]        # of the resident single-wave workgroups
 DRAIN_FRACTIONS = [0.02, 0.08, 0.25]
+CHUNKS = [2, 4, 16, 32]            # second round (the first uses the default 8)
 
 
 def candidates(device, free_mask=0xFF):
@@ -102,13 +107,20 @@ def tune_queue(batch: DeviceBatch, rec: torch.Tensor, opts=None, sample: int = 6
         idx = torch.linspace(0, batch.n - 1, sub.n, device=batch.device).long()
         sub_rec = rec[idx].contiguous()
     timings = []
-    for c, d in candidates(batch.device, opts.free_mask):
+
+    def run(c, d):
         cfg = queue_cfg(**c)
         time_queue(sub, sub_rec, opts, cfg, d)           # warm-up
         ms = min(time_queue(sub, sub_rec, opts, cfg, d) for _ in range(2))
         timings.append(dict(cfg=c, drain_frac=d, ms=ms))
         if verbose:
             print("autotune", c, d, "%.3f ms" % ms, flush=True)
+
+    for c, d in candidates(batch.device, opts.free_mask):
+        run(c, d)
+    first = min(timings, key=lambda t: t["ms"])
+    for k in CHUNKS:
+        run(dict(first["cfg"], chunk=k), first["drain_frac"])
     best = min(timings, key=lambda t: t["ms"])
     if use_cache:
         try:

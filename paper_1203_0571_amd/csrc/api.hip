@@ -60,6 +60,7 @@ int check_queue(const shape_batch* b, const shape_opts* o, const shape_queue_cfg
   if (rc == SHAPE_OK) rc = check_opts(o);
   if (rc != SHAPE_OK) return rc;
   if (!c || (c->team != 1 && c->team != 2 && c->team != 4) || c->grid < 0) return SHAPE_EINVAL;
+  if (c->chunk < 0 || c->chunk > 64) return SHAPE_EINVAL;
   if (c->team > 1 && (c->team_min_side < kMinSide || c->team_min_side > kMaxSide))
     return SHAPE_EINVAL;
   if (b->n > 0x7fffffffll) return SHAPE_EINVAL;
@@ -77,6 +78,7 @@ QCfg qcfg(const shape_queue_cfg* c) {
   q.team = c->team;
   q.team_min_side = c->team_min_side;
   q.grid = c->grid;
+  q.chunk = c->chunk;
   return q;
 }
 
@@ -237,7 +239,7 @@ int shape_queue_default_cfg(shape_queue_cfg* c) {
   c->team = 1;
   c->team_min_side = 96;
   c->grid = 0;
-  c->reserved = 0;
+  c->chunk = 0;
   return SHAPE_OK;
 }
 

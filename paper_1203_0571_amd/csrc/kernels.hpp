@@ -20,6 +20,7 @@ struct QCfg {
   int team;           // waves per stamp for large stamps: 1, 2 or 4
   int team_min_side;  // stamps with side >= this are taken by a team
   int grid;           // persistent workgroups; 0 = all that fit on the device
+  int chunk;          // stamps per cursor pop at most; 0 = the default
 };
 
 // Workspace layout of the queue form: a 256-byte header, the cursor lines,

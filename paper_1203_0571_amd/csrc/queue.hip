@@ -33,7 +33,7 @@
 namespace shape {
 namespace {
 
-constexpr uint32_t kMaxChunk = 8;   // stamps per cursor pop at most
+constexpr uint32_t kMaxChunk = 8;   // stamps per cursor pop at most, by default
 constexpr int kDecideBlock = 256;
 // The decide pass's FP64 bookkeeping holds a stamp's 45 sums and its damped
 // system in one lane: waves per SIMD against register spills.
@@ -333,18 +333,18 @@ __global__ __launch_bounds__(kDecideBlock) void start_kernel(shape_batch b, KOpt
 // ... of the class (every cursor sees the whole size mix); a wave starts on
 // cursor (its index mod kCursors, so consecutive workgroups, which go to
 // different XCDs, use different cursors) and moves on when that one is
-// drained, so the grid drains every cursor.  Chunks shrink from kMaxChunk to
-// one stamp as a cursor's part runs out.  Returns (q << 40 | cnt << 32 | j):
+// drained, so the grid drains every cursor.  Chunks shrink from maxc (the
+// configuration's chunk) to one stamp as a cursor's part runs out.  Returns (q << 40 | cnt << 32 | j):
 // positions q + kCursors (j .. j + cnt - 1), or ~0 when all are drained.
 __device__ inline uint64_t pop_chunk(uint32_t* cursors, uint32_t count, int& q, int& tried,
-                                     uint32_t per) {
+                                     uint32_t per, uint32_t maxc) {
   while (tried < kCursors) {
     const uint32_t part = count > (uint32_t)q ? (count - q + kCursors - 1) / kCursors : 0u;
     uint32_t* cur = cursors + q * kCursorStride;
     const uint32_t seen = __hip_atomic_load(cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (seen < part) {
       uint32_t k = (part - seen) / (2u * per);
-      k = k < 1u ? 1u : (k > kMaxChunk ? kMaxChunk : k);
+      k = k < 1u ? 1u : (k > maxc ? maxc : k);
       const uint32_t j = atomicAdd(cur, k);
       if (j < part) {
         const uint32_t cnt = part - j < k ? part - j : k;
@@ -381,7 +381,8 @@ __device__ __forceinline__ void sweep_one(const shape_batch& b, const Stamp& st,
 // 64 are staged whole for the row layout.  Four waves per SIMD, as the fused
 // fit.
 template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT>
-__global__ __launch_bounds__(kWave* TEAM, 4) void sweep_kernel(shape_batch b, void* ws) {
+__global__ __launch_bounds__(kWave* TEAM, 4) void sweep_kernel(shape_batch b, void* ws,
+                                                               uint32_t chunk) {
   __shared__ double xs[TEAM * kSums];
   __shared__ uint64_t s_pop;
   __shared__ __align__(16) unsigned char stage[TEAM][kStageBytes];
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(kWave* TEAM, 4) void sweep_kernel(shape_batch b, vo
     const uint32_t per = (gridDim.x + kCursors - 1) / kCursors;
     int q = blockIdx.x % kCursors, tried = 0;
     for (;;) {
-      if (tid == 0) s_pop = pop_chunk(cursors, count, q, tried, per);
+      if (tid == 0) s_pop = pop_chunk(cursors, count, q, tried, per, chunk);
       __syncthreads();
       const uint64_t pk = s_pop;
       __syncthreads();
@@ -419,7 +420,7 @@ __global__ __launch_bounds__(kWave* TEAM, 4) void sweep_kernel(shape_batch b, vo
   int q = (int)((blockIdx.x * TEAM + wave) % kCursors), tried = 0;
   for (;;) {
     uint64_t pk = 0;
-    if (lane == 0) pk = pop_chunk(cursors, count, q, tried, per);
+    if (lane == 0) pk = pop_chunk(cursors, count, q, tried, per, chunk);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)pk);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(pk >> 32));
     if (lo == ~0u && hi == ~0u) break;
@@ -811,7 +812,8 @@ hipError_t launch_step(const shape_batch& b, const KOpts& o, void* ws, const QCf
       hipError_t e = resident_grid(fn, cfg.team, &grid);
       if (e != hipSuccess) return e;
     }
-    void* args[] = {(void*)&b, &ws};
+    uint32_t chunk = cfg.chunk > 0 ? (uint32_t)cfg.chunk : kMaxChunk;
+    void* args[] = {(void*)&b, &ws, &chunk};
     hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kWave * cfg.team), args, 0, stream);
     if (e != hipSuccess) return e;
   }

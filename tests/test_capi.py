@@ -154,6 +154,10 @@ def test_queue_argument_errors(shape):
         cc = shape.queue_cfg(team=team, team_min_side=side)
         assert L.shape_queue_step(C.byref(b), C.byref(o), C.byref(cc), out, need,
                                   None) == shape.EINVAL
+    for chunk in (-1, 65):
+        cc = shape.queue_cfg(chunk=chunk)
+        assert L.shape_queue_step(C.byref(b), C.byref(o), C.byref(cc), out, need,
+                                  None) == shape.EINVAL
     # the 4-parameter mask runs one wave per stamp only
     o4 = shape.default_opts(free_mask=0xF0)
     c2 = shape.queue_cfg(team=2, team_min_side=64)

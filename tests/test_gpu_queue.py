@@ -56,17 +56,18 @@ def test_queue_equals_fused_fit(shape, workload):
             assert q["drained"] and q["steps"] == 2
 
 
-@pytest.mark.parametrize("grid", [1, 3, 8, 100])
-def test_queue_small_grids(shape, grid):
+@pytest.mark.parametrize("grid,chunk", [(1, 0), (3, 1), (8, 0), (100, 64)])
+def test_queue_small_grids(shape, grid, chunk):
     """Persistent grids smaller than the cursor count still drain every cursor
-    (a workgroup moves on to the next cursor when its own is empty)."""
+    (a workgroup moves on to the next cursor when its own is empty), at any
+    number of stamps per pop."""
     b = synth.make("uneven", count=512)
     db = shape.DeviceBatch.from_host(b, "cuda:0")
     o = shape.default_opts()
     rec = _moments(shape, db, o)
     fused = _np(shape.fit_sersic(db, rec=rec, opts=o))
-    q = _np(shape.fit_queue(db, rec=rec, opts=o, cfg=shape.queue_cfg(team=1, grid=grid),
-                            drain_at=0))
+    q = _np(shape.fit_queue(db, rec=rec, opts=o,
+                            cfg=shape.queue_cfg(team=1, grid=grid, chunk=chunk), drain_at=0))
     for k in ("p", "chi2", "iters", "status", "sweeps"):
         np.testing.assert_array_equal(q[k], fused[k], err_msg=k)
 
@@ -137,12 +138,13 @@ def test_autotuner_picks_a_measured_candidate(shape, tmp_path, monkeypatch):
     o = shape.default_opts()
     rec = _moments(shape, db, o)
     t = autotune.tune_queue(db, rec, o, sample=1024)
-    assert len(t["timings"]) == len(autotune.candidates(db.device, o.free_mask))
+    assert len(t["timings"]) == len(autotune.candidates(db.device, o.free_mask)) + \
+        len(autotune.CHUNKS)
     best = min(t["timings"], key=lambda x: x["ms"])
     cfg = t["cfg"]
-    assert (cfg.team, cfg.team_min_side, cfg.grid) == (best["cfg"]["team"],
-                                                        best["cfg"]["team_min_side"],
-                                                        best["cfg"]["grid"])
+    assert (cfg.team, cfg.team_min_side, cfg.grid, cfg.chunk) == (
+        best["cfg"]["team"], best["cfg"]["team_min_side"], best["cfg"]["grid"],
+        best["cfg"].get("chunk", 0))
     assert t["drain_frac"] == best["drain_frac"]
     t2 = autotune.tune_queue(db, rec, o, sample=1024)      # served from the cache
     assert (t2["cfg"].team, t2["cfg"].grid, t2["drain_frac"]) == (cfg.team, cfg.grid,

@@ -77,37 +77,41 @@ __global__ __launch_bounds__(kWave, SHAPE_FIT_WAVES_PER_SIMD) void fit_kernel(
   }
 }
 
+template <int DT, int MODEL, uint32_t MASK, bool PROF>
+void launch_layout(int layout, dim3 g, dim3 t, hipStream_t stream, const shape_batch& b,
+                   const KOpts& o, const float* p_init, const float* rec, float* p_out,
+                   float* chi2, float* perr, int32_t* iters, uint32_t* status, int32_t* sweeps) {
+  if (layout == kLayoutRows) {
+    if constexpr (MODEL == SHAPE_SERSIC)
+      hipLaunchKernelGGL((fit_kernel<DT, MODEL, MASK, kLayoutRows, PROF>), g, t, 0, stream, b, o,
+                         p_init, rec, p_out, chi2, perr, iters, status, sweeps);
+  } else if (layout == kLayoutAny) {
+    hipLaunchKernelGGL((fit_kernel<DT, MODEL, MASK, kLayoutAny, PROF>), g, t, 0, stream, b, o,
+                       p_init, rec, p_out, chi2, perr, iters, status, sweeps);
+  } else {
+    hipLaunchKernelGGL((fit_kernel<DT, MODEL, MASK, kLayoutSegs, PROF>), g, t, 0, stream, b, o,
+                       p_init, rec, p_out, chi2, perr, iters, status, sweeps);
+  }
+}
+
 template <int DT, int MODEL>
 void launch_fit_model(const shape_batch& b, const KOpts& o, const float* p_init,
                       const float* rec, float* p_out, float* chi2, float* perr, int32_t* iters,
                       uint32_t* status, int32_t* sweeps, hipStream_t stream) {
   const int64_t grid = b.n < (1ll << 30) ? b.n : (1ll << 30);
   const dim3 g((unsigned)grid), t(kWave);
-  // A batch of one side that divides 64 (no side array) takes the row layout.
-  const bool rows = MODEL == SHAPE_SERSIC && !b.side && !b.model && rows_layout_fits(b.side0);
+  const int layout = single_wave_layout(b, MODEL);
   if (!o.linear_init) {
     // the unprofiled form: Sersic, (Re, n, I0, sky) free (checked by the caller)
     if constexpr (MODEL != SHAPE_SERSIC) return;
-    if (rows)
-      hipLaunchKernelGGL((fit_kernel<DT, SHAPE_SERSIC, kMaskSize, kLayoutRows, false>), g, t, 0,
-                         stream, b, o, p_init, rec, p_out, chi2, perr, iters, status, sweeps);
-    else
-      hipLaunchKernelGGL((fit_kernel<DT, SHAPE_SERSIC, kMaskSize, kLayoutAny, false>), g, t, 0,
-                         stream, b, o, p_init, rec, p_out, chi2, perr, iters, status, sweeps);
+    launch_layout<DT, SHAPE_SERSIC, kMaskSize, false>(layout, g, t, stream, b, o, p_init, rec,
+                                                      p_out, chi2, perr, iters, status, sweeps);
   } else if (o.free_mask == kMaskAll) {
-    if (rows)
-      hipLaunchKernelGGL((fit_kernel<DT, MODEL, kMaskAll, kLayoutRows>), g, t, 0, stream, b, o,
-                         p_init, rec, p_out, chi2, perr, iters, status, sweeps);
-    else
-      hipLaunchKernelGGL((fit_kernel<DT, MODEL, kMaskAll, kLayoutAny>), g, t, 0, stream, b, o,
-                         p_init, rec, p_out, chi2, perr, iters, status, sweeps);
+    launch_layout<DT, MODEL, kMaskAll, true>(layout, g, t, stream, b, o, p_init, rec, p_out, chi2,
+                                             perr, iters, status, sweeps);
   } else {
-    if (rows)
-      hipLaunchKernelGGL((fit_kernel<DT, MODEL, kMaskSize, kLayoutRows>), g, t, 0, stream, b, o,
-                         p_init, rec, p_out, chi2, perr, iters, status, sweeps);
-    else
-      hipLaunchKernelGGL((fit_kernel<DT, MODEL, kMaskSize, kLayoutAny>), g, t, 0, stream, b, o,
-                         p_init, rec, p_out, chi2, perr, iters, status, sweeps);
+    launch_layout<DT, MODEL, kMaskSize, true>(layout, g, t, stream, b, o, p_init, rec, p_out,
+                                              chi2, perr, iters, status, sweeps);
   }
 }
 

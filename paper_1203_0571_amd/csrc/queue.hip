@@ -376,10 +376,12 @@ __device__ __forceinline__ void sweep_one(const shape_batch& b, const Stamp& st,
 // Persistent sweep pass over one model's classes of the current list: the
 // team class (TEAM waves per stamp), then every wave alone on the single
 // class.  Every stamp comes from memory (each step visits each stamp once,
-// so none is in the caches): stamps of any side stream through an LDS buffer
-// per wave in blocks (kLayoutStaged); FP16 stamps of one side that divides
-// 64 are staged whole for the row layout.  Four waves per SIMD, as the fused
-// fit.
+// so none is in the caches): a team streams its stamp through an LDS buffer
+// in blocks (kLayoutStaged); a wave alone takes the fused fit's layout
+// (single_wave_layout; FP16 stamps of a batch of one side that divides 64
+// staged whole in LDS, the lane-stride walk through an LDS buffer), so its
+// sums are the fused fit's bit for bit.  Four waves per
+// SIMD, as the fused fit.
 template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT>
 __global__ __launch_bounds__(kWave* TEAM, 4) void sweep_kernel(shape_batch b, void* ws,
                                                                uint32_t chunk) {
@@ -447,7 +449,10 @@ __global__ __launch_bounds__(kWave* TEAM, 4) void sweep_kernel(shape_batch b, vo
           sweep_one<DT, MODEL, MASK, 1, kLayoutRows>(b, st, v, r, nullptr, lane, nullptr);
         }
       } else {
-        sweep_one<DT, MODEL, MASK, 1, kLayoutStaged>(b, st, v, r, nullptr, lane, stage[wave]);
+        // the fused fit's layout: column segments, or the lane-stride walk
+        // (through the LDS buffer: the same sums)
+        constexpr int kL = LAYOUT == kLayoutSegs ? kLayoutSegsStaged : kLayoutStaged;
+        sweep_one<DT, MODEL, MASK, 1, kL>(b, st, v, r, nullptr, lane, stage[wave]);
       }
     }
   }
@@ -748,15 +753,15 @@ __global__ void finish_kernel(shape_batch b, KOpts o, void* ws, float* p_out, fl
 
 // ---- host side ------------------------------------------------------------
 
-template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT = kLayoutAny>
+template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT>
 const void* sweep_ptr() {
   return reinterpret_cast<const void*>(&sweep_kernel<DT, MODEL, MASK, TEAM, LAYOUT>);
 }
 
 template <int MODEL>
-const void* pick_sweep(int dtype, uint32_t mask, int team, bool rows) {
+const void* pick_sweep(int dtype, uint32_t mask, int team, int layout) {
   if constexpr (MODEL == SHAPE_SERSIC) {
-    if (rows && team == 1) {
+    if (layout == kLayoutRows && team == 1) {
       if (dtype == SHAPE_F32 && mask == kMaskAll)
         return sweep_ptr<SHAPE_F32, MODEL, kMaskAll, 1, kLayoutRows>();
       if (dtype == SHAPE_F32 && mask == kMaskSize)
@@ -767,8 +772,10 @@ const void* pick_sweep(int dtype, uint32_t mask, int team, bool rows) {
         return sweep_ptr<SHAPE_F16_SCALED, MODEL, kMaskSize, 1, kLayoutRows>();
     }
   }
-#define SHAPE_Q(DT, M, T) \
-  if (dtype == DT && mask == M && team == T) return sweep_ptr<DT, MODEL, M, T>();
+#define SHAPE_Q(DT, M, T)                                                   \
+  if (dtype == DT && mask == M && team == T)                                \
+    return layout == kLayoutSegs ? sweep_ptr<DT, MODEL, M, T, kLayoutSegs>() \
+                                 : sweep_ptr<DT, MODEL, M, T, kLayoutAny>();
   SHAPE_Q(SHAPE_F32, kMaskAll, 1)
   SHAPE_Q(SHAPE_F32, kMaskAll, 2)
   SHAPE_Q(SHAPE_F32, kMaskAll, 4)
@@ -802,10 +809,12 @@ hipError_t launch_step(const shape_batch& b, const KOpts& o, void* ws, const QCf
                        hipStream_t stream) {
   const QView v = view(ws, b.n);
   const int models = b.model ? 2 : 1;
-  const bool rows = !b.side && !b.model && rows_layout_fits(b.side0);
   for (int m = 0; m < models; ++m) {
-    const void* fn = m == 0 ? pick_sweep<SHAPE_SERSIC>(b.dtype, o.free_mask, cfg.team, rows)
-                            : pick_sweep<SHAPE_MOFFAT>(b.dtype, o.free_mask, cfg.team, rows);
+    const void* fn =
+        m == 0 ? pick_sweep<SHAPE_SERSIC>(b.dtype, o.free_mask, cfg.team,
+                                          single_wave_layout(b, SHAPE_SERSIC))
+               : pick_sweep<SHAPE_MOFFAT>(b.dtype, o.free_mask, cfg.team,
+                                          single_wave_layout(b, SHAPE_MOFFAT));
     if (!fn) return hipErrorInvalidValue;
     int grid = cfg.grid;
     if (grid <= 0) {
@@ -831,15 +840,15 @@ hipError_t launch_step(const shape_batch& b, const KOpts& o, void* ws, const QCf
   return hipGetLastError();
 }
 
-template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT = kLayoutAny>
+template <int DT, int MODEL, uint32_t MASK, int TEAM, int LAYOUT>
 const void* drain_ptr() {
   return reinterpret_cast<const void*>(&drain_kernel<DT, MODEL, MASK, TEAM, LAYOUT>);
 }
 
 template <int MODEL>
-const void* pick_drain(int dtype, uint32_t mask, int team, bool rows) {
+const void* pick_drain(int dtype, uint32_t mask, int team, int layout) {
   if constexpr (MODEL == SHAPE_SERSIC) {
-    if (rows && team == 1) {
+    if (layout == kLayoutRows && team == 1) {
       if (dtype == SHAPE_F32 && mask == kMaskAll)
         return drain_ptr<SHAPE_F32, MODEL, kMaskAll, 1, kLayoutRows>();
       if (dtype == SHAPE_F32 && mask == kMaskSize)
@@ -850,8 +859,10 @@ const void* pick_drain(int dtype, uint32_t mask, int team, bool rows) {
         return drain_ptr<SHAPE_F16_SCALED, MODEL, kMaskSize, 1, kLayoutRows>();
     }
   }
-#define SHAPE_D(DT, M, T) \
-  if (dtype == DT && mask == M && team == T) return drain_ptr<DT, MODEL, M, T>();
+#define SHAPE_D(DT, M, T)                                                   \
+  if (dtype == DT && mask == M && team == T)                                \
+    return layout == kLayoutSegs ? drain_ptr<DT, MODEL, M, T, kLayoutSegs>() \
+                                 : drain_ptr<DT, MODEL, M, T, kLayoutAny>();
   SHAPE_D(SHAPE_F32, kMaskAll, 1)
   SHAPE_D(SHAPE_F32, kMaskAll, 2)
   SHAPE_D(SHAPE_F32, kMaskAll, 4)
@@ -870,10 +881,12 @@ hipError_t launch_queue_drain(const shape_batch& b, const KOpts& o, void* ws, co
                               hipStream_t stream) {
   const QView v = view(ws, b.n);
   const int models = b.model ? 2 : 1;
-  const bool rows = !b.side && !b.model && rows_layout_fits(b.side0);
   for (int m = 0; m < models; ++m) {
-    const void* fn = m == 0 ? pick_drain<SHAPE_SERSIC>(b.dtype, o.free_mask, cfg.team, rows)
-                            : pick_drain<SHAPE_MOFFAT>(b.dtype, o.free_mask, cfg.team, rows);
+    const void* fn =
+        m == 0 ? pick_drain<SHAPE_SERSIC>(b.dtype, o.free_mask, cfg.team,
+                                          single_wave_layout(b, SHAPE_SERSIC))
+               : pick_drain<SHAPE_MOFFAT>(b.dtype, o.free_mask, cfg.team,
+                                          single_wave_layout(b, SHAPE_MOFFAT));
     if (!fn) return hipErrorInvalidValue;
     int grid = 0;
     hipError_t e = resident_grid(fn, cfg.team, &grid);

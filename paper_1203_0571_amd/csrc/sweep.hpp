@@ -281,8 +281,40 @@ constexpr int kLayoutRows = 1;
 // kLayoutAny, so the sums are the same bit for bit.
 constexpr int kLayoutStaged = 2;
 constexpr int kStageBytes = 8192;
+// kLayoutSegs: a wave alone on a stamp of any side, the stamp cut into column
+// segments of kSegRows rows (segment s: column s mod W, rows kSegRows (s / W)
+// on), lane l taking segments l, l + 64, ...: along a segment u1 is fixed, so
+// the geometry is the row layout's per-column quadratics, and a segment is
+// one FP32 partial of the chi^2 and J^T r sums.  Sides up to 64 take the
+// lane-stride walk: their segments fill the wave's last round less evenly
+// (measured on the 48 x 48 workload: fit 6.2 ms in segments, 6.05 ms
+// walking; on the uneven workload 82.2 ms with segments above side 64,
+// 88.9 ms walking every stamp).
+constexpr int kLayoutSegs = 3;
+constexpr int kSegRows = 8;
+constexpr int kSegsMinSide = 65;
+// kLayoutSegsStaged: the same, with the smaller stamps' walk through the LDS
+// buffer of kLayoutStaged (the same sums).
+constexpr int kLayoutSegsStaged = 4;
+
 __host__ __device__ inline constexpr bool rows_layout_fits(int side) {
   return side == 8 || side == 16 || side == 32 || side == 64;
+}
+
+// The layout of a wave alone on a stamp of batch b for the given model; the
+// fused fit and the work queue's single waves take the same one, so their
+// sums agree bit for bit: the row layout for a batch of one side that divides
+// 64 (Sersic stamps of a batch without a model array), the lane-stride walk
+// for a batch of one other side up to 64, column segments otherwise (a batch
+// of mixed sides walks its stamps up to side 64).  A batch of one side up to
+// 64 gets a kernel without the segment code: in a kernel that also holds it,
+// the walk spills more and ran slower (48 x 48 fit 6.85 ms instead of 6.05).
+inline int single_wave_layout(const shape_batch& b, int model) {
+  if (!b.side) {
+    if (model == SHAPE_SERSIC && !b.model && rows_layout_fits(b.side0)) return kLayoutRows;
+    if (b.side0 <= kWave) return kLayoutAny;
+  }
+  return kLayoutSegs;
 }
 
 // Pixels of a lane whose chi^2 and J^T r terms the FP32 instance sums in FP32
@@ -416,64 +448,111 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
         if (m % kFlush == kFlush - 1) flush();   // m is wave-uniform
     }
   } else {
-    int cnt = 0;
-    // pixel (i, j) with value d, in the lane-stride order of for_pixels
-    auto any_pixel = [&](const T d, int i, int j) {
-      const T u1 = (T)j - t.x0, u2 = (T)i - t.y0;
-      // (v1, v2) = S(e) u
-      const T v1 = A::fma(t.a11, u1, t.a12 * u2), v2 = A::fma(t.a12, u1, t.a22 * u2);
-      const T R2 = A::fma(v1, v1, v2 * v2) * t.invD;
-      pixel(d, R2, A::fma(t.n11, u1, t.n12 * u2), A::fma(t.n12, u1, t.n22 * u2),
-            A::fma(t.e1, R2, A::fma(v2, u2, -v1 * u1)), A::fma(t.e2, R2, -A::fma(v1, u2, v2 * u1)));
-      if constexpr (kFlush > 0) {
-        if (++cnt == kFlush) {
-          flush();
-          cnt = 0;
-        }
-      }
-    };
-    if constexpr (LAYOUT == kLayoutStaged) {
-      using E = typename std::conditional<DT == SHAPE_F32, float, _Float16>::type;
-      constexpr int kBlk = kStageBytes / (int)sizeof(E);
-      static_assert(kBlk % (STRIDE * (kFlush > 0 ? kFlush : 1)) == 0,
-                    "blocks keep the partial-sum cadence");
-      auto stage_sync = [] {
-        if constexpr (STRIDE == kWave)
-          wave_sync();
-        else
-          __syncthreads();
-      };
-      E* buf = static_cast<E*>(stage);
-      const E* src = static_cast<const E*>(b.pixels) + st.off;
-      const int side = st.side, npix = st.npix;
-      const int t0 = tid < 0 ? (int)(threadIdx.x & (kWave - 1)) : tid;
-      int i = t0 / side, j = t0 - i * side;
-      const int di = STRIDE / side, dj = STRIDE - di * side;
-      int k = t0;
-#pragma unroll 1
-      for (int k0 = 0; k0 < npix; k0 += kBlk) {
-        const int nb = npix - k0 < kBlk ? npix - k0 : kBlk;
-        stage_sync();   // the previous block's reads are done
-#pragma unroll 8
-        for (int q = t0; q < nb; q += STRIDE) buf[q] = src[k0 + q];
-        stage_sync();
-#pragma unroll 1
-        for (; k < k0 + nb; k += STRIDE) {
-          const E e = buf[k - k0];
-          const T d = DT == SHAPE_F32 ? (T)(float)e : (T)((float)e * st.scale);
-          any_pixel(d, i, j);
-          i += di;
-          j += dj;
-          if (j >= side) {
-            j -= side;
-            ++i;
+    // the lane-stride walk (any side, any team), directly or through LDS
+    auto any_walk = [&]() {
+      int cnt = 0;
+      // pixel (i, j) with value d, in the lane-stride order of for_pixels
+      auto any_pixel = [&](const T d, int i, int j) {
+        const T u1 = (T)j - t.x0, u2 = (T)i - t.y0;
+        // (v1, v2) = S(e) u
+        const T v1 = A::fma(t.a11, u1, t.a12 * u2), v2 = A::fma(t.a12, u1, t.a22 * u2);
+        const T R2 = A::fma(v1, v1, v2 * v2) * t.invD;
+        pixel(d, R2, A::fma(t.n11, u1, t.n12 * u2), A::fma(t.n12, u1, t.n22 * u2),
+              A::fma(t.e1, R2, A::fma(v2, u2, -v1 * u1)), A::fma(t.e2, R2, -A::fma(v1, u2, v2 * u1)));
+        if constexpr (kFlush > 0) {
+          if (++cnt == kFlush) {
+            flush();
+            cnt = 0;
           }
         }
+      };
+      if constexpr (LAYOUT == kLayoutStaged || LAYOUT == kLayoutSegsStaged) {
+        using E = typename std::conditional<DT == SHAPE_F32, float, _Float16>::type;
+        constexpr int kBlk = kStageBytes / (int)sizeof(E);
+        static_assert(kBlk % (STRIDE * (kFlush > 0 ? kFlush : 1)) == 0,
+                      "blocks keep the partial-sum cadence");
+        auto stage_sync = [] {
+          if constexpr (STRIDE == kWave)
+            wave_sync();
+          else
+            __syncthreads();
+        };
+        E* buf = static_cast<E*>(stage);
+        const E* src = static_cast<const E*>(b.pixels) + st.off;
+        const int side = st.side, npix = st.npix;
+        const int t0 = tid < 0 ? (int)(threadIdx.x & (kWave - 1)) : tid;
+        int i = t0 / side, j = t0 - i * side;
+        const int di = STRIDE / side, dj = STRIDE - di * side;
+        int k = t0;
+#pragma unroll 1
+        for (int k0 = 0; k0 < npix; k0 += kBlk) {
+          const int nb = npix - k0 < kBlk ? npix - k0 : kBlk;
+          stage_sync();   // the previous block's reads are done
+#pragma unroll 8
+          for (int q = t0; q < nb; q += STRIDE) buf[q] = src[k0 + q];
+          stage_sync();
+#pragma unroll 1
+          for (; k < k0 + nb; k += STRIDE) {
+            const E e = buf[k - k0];
+            const T d = DT == SHAPE_F32 ? (T)(float)e : (T)((float)e * st.scale);
+            any_pixel(d, i, j);
+            i += di;
+            j += dj;
+            if (j >= side) {
+              j -= side;
+              ++i;
+            }
+          }
+        }
+      } else {
+        for_pixels<STRIDE>(st.side, [&](int k, int i, int j) {
+          any_pixel((T)load_px<DT>(b.pixels, st.off, k, st.scale), i, j);
+        }, tid);
+      }
+  
+    };
+    if constexpr (LAYOUT == kLayoutSegs || LAYOUT == kLayoutSegsStaged) {
+      static_assert(STRIDE == kWave, "the segment layout is for a wave alone on its stamp");
+      if (st.side >= kSegsMinSide) {
+        const int lane = tid < 0 ? (int)(threadIdx.x & (kWave - 1)) : tid;
+        const int W = st.side, last = W - 1;
+        const int S = W * ((W + kSegRows - 1) / kSegRows);   // segments
+        const void* sp = stamp_base<DT>(b, st);
+#pragma unroll 1
+        for (int s0 = 0; s0 < S; s0 += kWave) {   // wave-uniform
+          const int sg = s0 + lane;
+          const bool on = sg < S;
+          const int g = on ? sg / W : 0, j = on ? sg - g * W : 0, r0 = g * kSegRows;
+          const T u1 = (T)j - t.x0;
+          const T uu = u1 * u1;
+          const T qb = t.qb1 * u1, qc = t.qc2 * uu;
+          const T p2b = t.e1 * qb, p2c = A::fma(t.e1, qc, -t.a11 * uu);
+          const T p3b = A::fma(t.e2, qb, (T)-2 * u1), p3c = A::fma(t.e2, qc, -t.a12 * uu);
+          const T c3 = t.n11 * u1, c4 = t.n12 * u1;
+          // the segment's pixels (rows past the stamp read its last row and are
+          // skipped below), loaded back to back
+          T d[kSegRows];
+#pragma unroll
+          for (int q = 0; q < kSegRows; ++q) {
+            const int i = r0 + q < last ? r0 + q : last;
+            d[q] = (T)load_rel<DT>(sp, (uint32_t)(i * W + j), st.scale);
+          }
+#pragma unroll
+          for (int q = 0; q < kSegRows; ++q) {
+            if (on && r0 + q < W) {
+              const T u2 = (T)(r0 + q) - t.y0;
+              pixel(d[q], A::fma(A::fma(t.qa, u2, qb), u2, qc), A::fma(t.n12, u2, c3),
+                    A::fma(t.n22, u2, c4), A::fma(A::fma(t.p2a, u2, p2b), u2, p2c),
+                    A::fma(A::fma(t.p3a, u2, p3b), u2, p3c));
+            }
+          }
+          flush();   // one partial per segment
+        }
+      } else {
+        any_walk();
       }
     } else {
-      for_pixels<STRIDE>(st.side, [&](int k, int i, int j) {
-        any_pixel((T)load_px<DT>(b.pixels, st.off, k, st.scale), i, j);
-      }, tid);
+      any_walk();
     }
   }
   flush();

@@ -68,7 +68,10 @@ FIT_SOURCES = ["paper_1203_0571_amd/csrc/fit.hip", "paper_1203_0571_amd/csrc/lm.
 FRAME_SOURCES = ["paper_1203_0571_amd/csrc/frames.hip", "paper_1203_0571_amd/csrc/common.hpp",
                  "paper_1203_0571_amd/csrc/bn_table.h", "paper_1203_0571_amd/csrc/kernels.hpp",
                  "include/shape.h", "paper_1203_0571_amd/build.py"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fit_sersic64h_hbm_traffic.md")
+# Counter summaries holding the fit's FETCH_SIZE / WRITE_SIZE per workload
+TRAFFIC_FILES = {"sersic64h": os.path.join(ROOT, "profiles", "fit_sersic64h_hbm_traffic.md"),
+                 "plain48": os.path.join(ROOT, "profiles", "pipeline_plain48_counters.md"),
+                 "uneven": os.path.join(ROOT, "profiles", "pipeline_uneven_counters.md")}
 FRAME_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "frame_detect_frames512_hbm_traffic.md")
 
 
@@ -103,9 +106,11 @@ def counter_traffic(path, files, form=""):
             float(kv["write_kib" + sfx]) * float(kv["write_scale"])) * 1024.0
 
 
-def fit_traffic_bytes(form):
-    """HBM bytes per launch of the fused fit for form "plain" or "f16"."""
-    return counter_traffic(TRAFFIC_FILE, FIT_SOURCES, form)
+def fit_traffic_bytes(workload, form):
+    """HBM bytes per launch of the fit of `workload` in the given form (None
+    where no counters were taken for that pair)."""
+    path = TRAFFIC_FILES.get(workload)
+    return counter_traffic(path, FIT_SOURCES, form) if path else None
 
 
 def log(*a):
@@ -394,8 +399,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "fit (" + chosen + ")",
                      "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                     "traffic": fit_traffic_bytes(chosen) if (chosen in ("plain", "f16") and
-                                                              wl == "sersic64h") else None,
+                     "traffic": fit_traffic_bytes(wl, chosen),
                      "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "launch_ms": round(rc["fit_ms"], 4),
                      "flop_per_pixel_sweep": FLOP_PER_PIXEL_SWEEP,
@@ -512,7 +516,10 @@ def bench_uneven(args):
             "roofline": {"bound": "alu", "kernel": "fit (" + best + ")",
                          "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                         "traffic": None, "launch_ms": round(r["fit_ms"], 3)}}
+                         "traffic": fit_traffic_bytes("uneven", best),
+                         "traffic_unit": "bytes per fit call (its Sersic and Moffat launches; "
+                                         "FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                         "launch_ms": round(r["fit_ms"], 3)}}
     print(json.dumps(line), flush=True)
 
 

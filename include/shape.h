@@ -332,7 +332,7 @@ int shape_queue_graph_destroy(shape_queue_graph* graph);
  * shape_fit_sersic plus the queue configuration; it runs shape_queue_start,
  * max_iter_lm steps (a step finds no work once every stamp is done) and
  * shape_queue_finish, with the workspace in a static device array of the
- * library (queue workspace of SHAPE_STATIC_MAX_STAMPS stamps, about 69 MB,
+ * library (queue workspace of SHAPE_STATIC_MAX_STAMPS stamps, about 67 MB,
  * held on every device the library runs on until the process ends).  The
  * results equal those of the three calls with a caller's workspace.
  *   n > SHAPE_STATIC_MAX_STAMPS returns SHAPE_ENOMEM before any work.

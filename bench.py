@@ -592,7 +592,15 @@ def bench_stars(args):
             "roofline": {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
                          "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
-                         "launch_ms": round(ms[dom], 4)}}
+                         "launch_ms": round(ms[dom], 4),
+                         "flop_per_pixel_step": {"centroid": FLOP_PER_PIXEL_CENTROID,
+                                                 "moments": FLOP_PER_PIXEL_MOMENTS,
+                                                 "star_moments": FLOP_PER_PIXEL_STAR_MOFFAT},
+                         "per_kernel": {k: {"ms": round(ms[k], 4),
+                                            "achieved": round(flop[k] / (ms[k] * 1e-3) / 1e12, 3),
+                                            "frac": round(flop[k] / (ms[k] * 1e-3) / 1e12
+                                                          / ALU_PEAK_TFLOPS, 4)}
+                                        for k in ms}}}
     # the paper's remedy for the rd-beta degeneracy (Sec. 4.2.2): beta fixed,
     # here at the workload's mean (3.75), rd and I0 from r0 and r2
     r1 = shape.moments(db, shape.centroid(db, opts)[0], opts)[0]

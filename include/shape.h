@@ -235,6 +235,10 @@ int shape_chi2_bwd(const shape_batch* batch, const float* params, const float* g
  * is below tol (the paper: 1e-4) or after max_iter steps (the paper: 20).
  * The weight starts at sigma_w of rec (Gaussian) or r50/sqrt(sqrt(2) - 1), the
  * beta = 3 Moffat whose half-light radius is the record's r50 (Moffat).
+ * Precision: for tol >= 1e-5 the sums and the step run in FP32 (their
+ * rounding, ~1e-7 relative, is far below such a tol); a smaller tol takes an
+ * FP64 instance of the sums and the step (slower), since FP32 rounding would
+ * keep the fractional change from falling below it.
  *   out [n][4] out: sigma or rd, beta (0 for Gaussian), I0, r0 of the last step
  *   iters, status [n] out.
  */

@@ -194,6 +194,34 @@ __device__ inline void wave_sum_n(double (&u)[N]) {
   for (int i = 0; i < N; ++i) u[i] = t[i];
 }
 
+// The same for N FP32 values.
+template <int N>
+__device__ inline void wave_sum_n(float (&u)[N]) {
+  static_assert(N % 4 == 0, "N must be a multiple of 4");
+  constexpr int H = N / 2, Q = N / 4;
+#pragma unroll
+  for (int j = 0; j < H; ++j) swap_add32(u[j], u[j + H]);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) swap_add16(u[j], u[j + Q]);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    u[j] = dpp::add<dpp::kShr1, 0xf>(u[j]);
+    u[j] = dpp::add<dpp::kShr2, 0xf>(u[j]);
+    u[j] = dpp::add<dpp::kShr4, 0xf>(u[j]);
+    u[j] = dpp::add<dpp::kShr8, 0xf>(u[j]);
+  }
+  float t[N];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+      t[Q * k + j] = __builtin_bit_cast(
+          float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, u[j]), 16 * k + 15));
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] = t[i];
+}
+
 // Walk the pixels owned by thread `tid` of a team of STRIDE threads working on
 // one stamp: k = tid, tid + STRIDE, ... with (row, col).
 template <int STRIDE = kWave, class F>

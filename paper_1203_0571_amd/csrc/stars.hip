@@ -20,6 +20,17 @@
 // stamps recompute them from the stamp on every step.  (Two 32 x 32 stamps per
 // wave, each on a half-wave, ran slower: a wave then iterates as long as the
 // slower of its two stars.)
+//
+// Precision (type T of the sums and of the step's closed forms): with 16
+// pixels per lane the step's reductions and closed forms cost as much as the
+// pixels, and in FP64 they took about 40% of the step.  For tolerances of
+// kStarExactTol and above T is FP32: a lane's at most 16 register pixels are
+// summed in FP32 (larger stamps' lanes in FP32 runs of 8 pixels carried in
+// FP64), and the wave sum and the closed forms run in FP32; the sums' rounding
+// (~1e-7 relative, reaching beta amplified by about beta) stays far below such
+// a tolerance and the 1e-3 agreement with the FP64 oracle.  Tighter
+// tolerances would stop on that rounding, so they take T = FP64: FP32 runs of
+// 8 pixels carried in FP64, FP64 wave sums and closed forms.
 #include "kernels.hpp"
 
 namespace shape {
@@ -27,6 +38,12 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kCache = 16;   // side <= 32
+constexpr double kStarExactTol = 1e-5;
+
+__device__ __forceinline__ float star_rcp(float x) { return fast_rcp(x); }
+__device__ __forceinline__ double star_rcp(double x) { return rcp_f64(x); }   // Newton
+__device__ __forceinline__ float star_sqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double star_sqrt(double x) { return sqrt(x); }
 
 struct StarGeom {
   float x0, y0, a11, a12, a22, invD, sky;
@@ -39,8 +56,9 @@ __device__ inline float star_r2(const StarGeom& G, int i, int j) {
 }
 
 // One pixel's terms of r0, r2, r4, added to FP32 partials s[0..2].
-template <int PROFILE>
-__device__ __forceinline__ void star_accumulate(float f, float R2, float c, float (&s)[3]) {
+template <int PROFILE, int N>
+__device__ __forceinline__ void star_accumulate(float f, float R2, float c, float (&s)[N]) {
+  static_assert(N >= 3, "three partial sums");
   float W;
   if constexpr (PROFILE == 0) {
     W = fast_exp2(-R2 * c);
@@ -62,10 +80,10 @@ constexpr int kStarBlock = 8;
 __host__ __device__ constexpr bool moffat_weight(int profile) { return profile != 0; }
 
 // The weight's constant for width w (w > 0).
-template <int PROFILE>
-__device__ __forceinline__ float weight_const(double w) {
-  const double iw2 = rcp_f64(w * w);
-  return (float)(moffat_weight(PROFILE) ? iw2 : 0.5 * kLog2e * iw2);
+template <int PROFILE, typename T>
+__device__ __forceinline__ float weight_const(T w) {
+  const T iw2 = star_rcp(w * w);
+  return (float)(moffat_weight(PROFILE) ? iw2 : (T)(0.5 * kLog2e) * iw2);
 }
 
 // The starting width: the Gaussian's sigma_w, or the Moffat (beta = 3, or
@@ -80,32 +98,31 @@ __device__ __forceinline__ double start_width(const float (&r)[SHAPE_REC_LEN], d
 
 // One step from the sums (s0, s2, s4) = (r0, r2, r4): the new size, and beta
 // for the free Moffat; false when the step cannot be taken (status in stt).
-template <int PROFILE>
-__device__ __forceinline__ bool star_step(double s0, double s2, double s4, double& beta,
-                                          double& ns, uint32_t& stt) {
-  if (!(s0 > 0.0) || !(s2 > 0.0)) {
+template <int PROFILE, typename T>
+__device__ __forceinline__ bool star_step(T s0, T s2, T s4, T& beta, T& ns, uint32_t& stt) {
+  if (!(s0 > (T)0) || !(s2 > (T)0)) {
     stt |= SHAPE_ST_NONPOSITIVE_FLUX;
     return false;
   }
-  const double is0 = rcp_f64(s0);   // s0, s2 > 0 here; reciprocals by Newton
+  const T is0 = star_rcp(s0);   // s0, s2 > 0 here
   if constexpr (PROFILE == 0) {
-    ns = sqrt(s2 * is0);
+    ns = star_sqrt(s2 * is0);
   } else {
     if constexpr (PROFILE == 1) {
-      const double is2 = rcp_f64(s2);
-      const double q = 0.5 * s4 * s0 * is2 * is2 - 1.0;
-      if (!(q > 0.0)) {
+      const T is2 = star_rcp(s2);
+      const T q = (T)0.5 * (s4 * is2) * (s0 * is2) - (T)1;
+      if (!(q > (T)0)) {
         stt |= SHAPE_ST_SINGULAR;
         return false;
       }
-      beta = rcp_f64(q);
+      beta = star_rcp(q);
     }
-    ns = sqrt(s2 * is0 * (beta + 1.0));
+    ns = star_sqrt(s2 * is0 * (beta + (T)1));
   }
   return true;
 }
 
-template <int DT, int PROFILE>
+template <int DT, int PROFILE, typename T>
 __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float* rec, double tol,
                                                      int max_iter, double beta_fixed, float* out,
                                                      int32_t* iters, uint32_t* status) {
@@ -151,28 +168,42 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
         }
       }
     }
-    double w = start_width<PROFILE>(r, beta_fixed);
-    double size = w, beta = PROFILE == 2 ? beta_fixed : 0.0, I0 = 0.0, r0 = 0.0, s0_ok = 0.0;
+    T w = (T)start_width<PROFILE>(r, beta_fixed);
+    T size = w, beta = PROFILE == 2 ? (T)beta_fixed : (T)0, r0 = 0, s0_ok = 0;
+    const T tolt = (T)tol;
     uint32_t stt = 0;
     int it = 0;
     while (it < max_iter) {
       const float c = weight_const<PROFILE>(w);   // w > 0: the start and every new size
-      double u[4] = {0.0, 0.0, 0.0, 0.0};   // r0, r2, r4 (and a pad)
-      float sp[3] = {0.0f, 0.0f, 0.0f};
-      auto carry = [&]() {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          u[q] += (double)sp[q];
-          sp[q] = 0.0f;
-        }
-      };
+      T u[4] = {0, 0, 0, 0};   // r0, r2, r4 (and a pad)
       if (cached) {
+        if constexpr (sizeof(T) == 4) {
 #pragma unroll
-        for (int q = 0; q < kCache; ++q) {
-          star_accumulate<PROFILE>(cf[q], cr[q], c, sp);
-          if (q % kStarBlock == kStarBlock - 1) carry();
+          for (int q = 0; q < kCache; ++q) star_accumulate<PROFILE>(cf[q], cr[q], c, u);
+        } else {
+          float sp[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int q = 0; q < kCache; ++q) {
+            star_accumulate<PROFILE>(cf[q], cr[q], c, sp);
+            if (q % kStarBlock == kStarBlock - 1) {
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                u[k] += (T)sp[k];
+                sp[k] = 0.0f;
+              }
+            }
+          }
         }
       } else {
+        double ud[3] = {0.0, 0.0, 0.0};
+        float sp[3] = {0.0f, 0.0f, 0.0f};
+        auto carry = [&]() {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            ud[q] += (double)sp[q];
+            sp[q] = 0.0f;
+          }
+        };
         int cnt = 0;
         for_pixels(st.side, [&](int k, int i, int j) {
           const float f = load_px<DT>(b.pixels, st.off, k, st.scale) - G.sky;
@@ -182,15 +213,17 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
             cnt = 0;
           }
         });
+        carry();
+#pragma unroll
+        for (int q = 0; q < 3; ++q) u[q] = (T)ud[q];
       }
-      carry();
       wave_sum_n(u);
-      const double s0 = u[0], s2 = u[1], s4 = u[2];
+      const T s0 = u[0], s2 = u[1], s4 = u[2];
       ++it;
       r0 = s0;
-      double ns;
+      T ns;
       if (!star_step<PROFILE>(s0, s2, s4, beta, ns, stt)) break;
-      const bool small = fabs(ns - w) < tol * ns;   // fractional change below tol
+      const bool small = fabs(ns - w) < tolt * ns;   // fractional change below tol
       size = ns;
       w = ns;
       s0_ok = s0;
@@ -200,7 +233,10 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
       }
     }
     // I0 of the last completed step (0 if none)
-    if (s0_ok > 0.0) I0 = (PROFILE == 0 ? s0_ok : s0_ok * (beta + 2.0)) / (kPi * size * size);
+    double I0 = 0.0;
+    if (s0_ok > (T)0)
+      I0 = (PROFILE == 0 ? (double)s0_ok : (double)s0_ok * ((double)beta + 2.0)) /
+           (kPi * (double)size * (double)size);
     if (!(stt & (SHAPE_ST_CONVERGED | SHAPE_ST_NONPOSITIVE_FLUX | SHAPE_ST_SINGULAR)))
       stt |= SHAPE_ST_MAX_ITER;
     if (lane == 0) {
@@ -218,9 +254,13 @@ template <int DT, int PROFILE>
 void launch_one(const shape_batch& b, const float* rec, double tol, int max_iter, double beta,
                 float* out, int32_t* iters, uint32_t* status, hipStream_t stream) {
   const int64_t cap = 1ll << 30;
-  const int64_t grid = b.n < cap ? b.n : cap;
-  hipLaunchKernelGGL((star_kernel<DT, PROFILE>), dim3((unsigned)grid), dim3(kWave), 0, stream, b,
-                     rec, tol, max_iter, beta, out, iters, status);
+  const dim3 grid((unsigned)(b.n < cap ? b.n : cap));
+  if (tol >= kStarExactTol)
+    hipLaunchKernelGGL((star_kernel<DT, PROFILE, float>), grid, dim3(kWave), 0, stream, b, rec,
+                       tol, max_iter, beta, out, iters, status);
+  else
+    hipLaunchKernelGGL((star_kernel<DT, PROFILE, double>), grid, dim3(kWave), 0, stream, b, rec,
+                       tol, max_iter, beta, out, iters, status);
 }
 
 template <int DT>

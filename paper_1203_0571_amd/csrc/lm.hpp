@@ -13,9 +13,9 @@
 //   dl = A_LL^-1 g_L,  chi2* = chi2 - g_L . dl,  s = I0* / I0,
 //   A*_NN = s^2 A_NN,  A*_NL = s A_NL,  g*_N = s (g_N - A_NL dl),  g*_L = 0.
 // The step in the free shape parameters solves (M + lambda diag M) d = g*_N,
-// M = A*_NN - A*_NL (A*_LL)^-1 A*_LN, in FP64 by Gauss-Jordan elimination
-// across the lanes of the team's first wave (lane r holds row r), from the
-// reduced sums kept in LDS.
+// M = A*_NN - A*_NL (A*_LL)^-1 A*_LN, in FP64 by an L D L^T factorisation
+// (the entries of M formed one per thread into LDS, the factorisation and
+// solve in one thread), from the reduced sums kept in LDS.
 #pragma once
 
 #include "sweep.hpp"
@@ -65,71 +65,46 @@ __device__ __forceinline__ void store_L(LmShared& W, const LmState& L, int tid) 
 }
 __device__ __forceinline__ LmState load_L(const LmShared& W) { return W.L; }
 
-// A double as lane l holds it (the same value in every lane).
-__device__ __forceinline__ double read_lane(double v, int l) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, l);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), l);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// Gauss-Jordan elimination across the lanes of one wave for an SPD system:
-// lane r < N holds row r of [A | B] in a[] and b[] (lanes >= N hold zeros).
-// No pivoting is needed (A is SPD: every pivot is positive); each step
-// broadcasts the pivot row with readlane, so the whole matrix never sits in
-// one lane's registers.  Afterwards lane r holds row r of A^-1 B in b[].
-// Returns false (on every lane) if a pivot is not positive.  Every lane of
-// the wave must call it.
-template <int N, int M>
-__device__ __forceinline__ bool gj_solve(double (&a)[N], double (&b)[M], int lane) {
-  bool ok = true;
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    const double piv = read_lane(a[j], j);
-    ok = ok && piv > 0.0;
-    const double ip = rcp_f64(piv);   // (a pivot that is not positive fails the solve)
-    const double f = (lane == j) ? 0.0 : a[j];
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-      const double pc = read_lane(a[c], j) * ip;
-      a[c] = (lane == j) ? pc : fma(-f, pc, a[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-      const double pc = read_lane(b[c], j) * ip;
-      b[c] = (lane == j) ? pc : fma(-f, pc, b[c]);
-    }
-  }
-  return ok;
-}
-
-// The same elimination as gj_solve within one lane (a[r] = row r): every
-// value is formed by the same operations in the same order, so the result is
-// bit-identical to the cross-lane form.  Used where one lane owns a stamp.
+// Solves the SPD system m x = b in one thread, m given as its lower triangle
+// row by row (m[i (i + 1) / 2 + j], j <= i), by the factorisation
+// m = L D L^T (L unit lower triangular, D diagonal): no square roots, one
+// reciprocal per pivot, about 120 FP64 operations for six unknowns.  x holds
+// b on entry and the solution on exit.  Returns false if a pivot is not
+// positive (x is then meaningless).  The fused fit and the batched form call
+// it on the same damped system, so both take the same step bit for bit.
 template <int N>
-__device__ __forceinline__ bool gj_serial(double (&a)[N][N], double (&b)[N]) {
+__device__ __forceinline__ bool ldl_solve(const double (&m)[N * (N + 1) / 2], double (&x)[N]) {
+  double L[N][N];   // the strictly lower part is used
+  double id[N];     // 1 / D
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    const double piv = a[j][j];
-    ok = ok && piv > 0.0;
-    const double ip = rcp_f64(piv);
-    double pr[N];
+    double u[N];    // u_k = L_jk D_k
 #pragma unroll
-    for (int c = 0; c < N; ++c) pr[c] = a[j][c] * ip;
-    const double pb = b[j] * ip;
+    for (int k = 0; k < j; ++k) {
+      double w = m[j * (j + 1) / 2 + k];
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-      if (r == j) continue;
-      const double f = a[r][j];
-#pragma unroll
-      for (int c = 0; c < N; ++c) a[r][c] = fma(-f, pr[c], a[r][c]);
-      b[r] = fma(-f, pb, b[r]);
+      for (int l = 0; l < k; ++l) w = fma(-u[l], L[k][l], w);
+      u[k] = w;
+      L[j][k] = w * id[k];
     }
+    double d = m[j * (j + 1) / 2 + j];
 #pragma unroll
-    for (int c = 0; c < N; ++c) a[j][c] = pr[c];
-    b[j] = pb;
+    for (int k = 0; k < j; ++k) d = fma(-u[k], L[j][k], d);
+    ok = ok && d > 0.0;
+    id[j] = rcp_f64(d);
   }
+  // L y = b, z = D^-1 y, L^T x = z
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int k = 0; k < i; ++k) x[i] = fma(-L[i][k], x[k], x[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] *= id[i];
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i)
+#pragma unroll
+    for (int k = i + 1; k < N; ++k) x[i] = fma(-L[k][i], x[k], x[i]);
   return ok;
 }
 
@@ -545,28 +520,14 @@ __device__ __forceinline__ void lm_iterate(const shape_batch& b, const KOpts& o,
     W.M[tid] = v;
   }
   team_sync<TEAM>();
-  // Phase 1b: the first wave solves the damped system (lane r < NN holds row
-  // r), then one thread forms the trial point.
-  double xr = 0.0;
-  bool solved = false;
-  if (tid < kWave) {
-    double a[NN], rhs[1];
-#pragma unroll
-    for (int c = 0; c < NN; ++c) {
-      const int hi = tid > c ? tid : c, lo = tid > c ? c : tid;
-      a[c] = tid < NN ? W.M[hi * (hi + 1) / 2 + lo] : 0.0;
-    }
-    rhs[0] = 0.0;
-#pragma unroll
-    for (int r = 0; r < NN; ++r)
-      if (tid == r) rhs[0] = W.sums[cur][sg(nth_bit(NL, r))];
-    solved = gj_solve<NN, 1>(a, rhs, tid);
-    xr = rhs[0];
-  }
-  double x[NN];
-#pragma unroll
-  for (int r = 0; r < NN; ++r) x[r] = read_lane(xr, r);
+  // Phase 1b: one thread solves the damped system and forms the trial point.
   if (tid == 0) {
+    double m[NT], x[NN];
+#pragma unroll
+    for (int e = 0; e < NT; ++e) m[e] = W.M[e];
+#pragma unroll
+    for (int a = 0; a < NN; ++a) x[a] = W.sums[cur][sg(nth_bit(NL, a))];
+    const bool solved = ldl_solve<NN>(m, x);
     LmState L = W.L;
     W.smax = lm_propose<MODEL, NL, LIN, NN>(L, step_rhs<NL, NN>(W.sums[cur]), x, solved, o, st,
                                             W.pt);

@@ -9,7 +9,7 @@
 //                   current list from atomic cursors, largest side first.
 //   decide kernel   one lane per stamp: profiles the amplitudes of the sweep,
 //                   accepts or rejects the trial, forms the damped Schur
-//                   complement, solves it (FP64 Gauss-Jordan within the lane)
+//                   complement, solves it (FP64 L D L^T within the lane)
 //                   and either finishes the stamp or forms the next trial's
 //                   constants and appends the stamp to the next list.
 //
@@ -550,19 +550,18 @@ __device__ bool decide_one(const shape_batch& b, const KOpts& o, const QView& v,
       break;
     }
     // the damped system and the step
-    double A[NN][NN], x[NN];
+    double A[NT], x[NN];
 #pragma unroll
     for (int a = 0, e = 0; a < NN; ++a) {
 #pragma unroll
       for (int c = 0; c <= a; ++c, ++e) {
         double d = M[e];
         if (a == c) d *= 1.0 + L.lambda;
-        A[a][c] = d;
-        A[c][a] = d;
+        A[e] = d;
       }
       x[a] = R.g[a];
     }
-    const bool solved = gj_serial<NN>(A, x);
+    const bool solved = ldl_solve<NN>(A, x);
     double pt[8];
     const double smax = lm_propose<MODEL, NL, LIN, NN>(L, R, x, solved, o, st, pt);
     if (smax >= 0.0) {

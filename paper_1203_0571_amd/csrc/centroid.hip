@@ -301,6 +301,189 @@ __global__ __launch_bounds__(kWave, SHAPE_CENTROID_WAVES_PER_SIMD) void centroid
   }
 }
 
+// Two 32 x 32 stamps per wave (stamps 2 w and 2 w + 1 of workgroup w's turn;
+// lanes 32 g + j hold column j of stamp g, all 32 rows): the same three passes
+// as centroid_kernel with every reduction taken per half-wave, and the
+// iteration running until both stamps stop (a stopped stamp's lanes idle).
+// A lane then sums 32 pixels per step, where the one-stamp form sums 16 and
+// each stamp's step pays the whole wave's reductions.
+constexpr int kPairRings = 48;   // ring_of(2 * 31^2) + 1 = 45, rounded up
+template <int DT>
+__global__ __launch_bounds__(kWave, 5) void centroid_pair_kernel(shape_batch b, KOpts o,
+                                                                 float* rec, int32_t* iters,
+                                                                 uint32_t* status) {
+  constexpr int W = kPairSide, kSlots = kPairSide;
+  __shared__ unsigned long long ring[2 * kPairRings];
+  __shared__ float wy_row[2 * W];
+  const int lane = threadIdx.x, g = lane >> 5, jl = lane & (W - 1);
+  const bool hi = g != 0;
+  for (int64_t s0 = 2 * (int64_t)blockIdx.x; s0 < b.n; s0 += 2 * (int64_t)gridDim.x) {
+    const int64_t s = s0 + g < b.n ? s0 + g : s0;   // a missing second stamp repeats the first
+    const bool own = s0 + g < b.n;                  // and writes nothing
+    const Stamp st = stamp_info(b, s);
+    float* out = rec + s * SHAPE_REC_LEN;
+    float v[kSlots];
+    {
+      const void* sp = stamp_base<DT>(b, st);
+      const bool ok = !st.bad;
+#pragma unroll
+      for (int m = 0; m < kSlots; ++m)
+        v[m] = ok ? load_rel<DT>(sp, (uint32_t)(m * W + jl), st.scale) : 0.0f;
+    }
+    // Pass 1: finiteness, border sum, brightest pixel, largest |I|.
+    double border = 0.0;
+    float best = -__builtin_huge_valf(), vmin = __builtin_huge_valf();
+    int besti = 0x7fffffff;
+    bool nonfinite = false;
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m) {
+      nonfinite |= !__builtin_isfinite(v[m]);
+      if (v[m] > best) {  // the index increases with m, so ties keep the lowest
+        best = v[m];
+        besti = m * W + jl;
+      }
+      vmin = fminf(vmin, v[m]);
+    }
+    float amax = fmaxf(fabsf(best), fabsf(vmin));
+    if (jl == 0 || jl == W - 1) {
+#pragma unroll
+      for (int m = 0; m < kSlots; ++m) border += (double)v[m];
+    } else {
+      border = (double)v[0] + (double)v[kSlots - 1];
+    }
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) {
+      const float ov = __shfl_xor(best, m, kWave);
+      const int oi = __shfl_xor(besti, m, kWave);
+      if (ov > best || (ov == best && oi < besti)) {
+        best = ov;
+        besti = oi;
+      }
+      amax = fmaxf(amax, __shfl_xor(amax, m, kWave));
+    }
+    {
+      double bu[2] = {border, 0.0};
+      half_sum_n(bu);
+      border = bu[0];
+    }
+    uint32_t stt = st.bad ? st.bad : (half_any(nonfinite) ? SHAPE_ST_NONFINITE_INPUT : 0u);
+    const bool live = stt == 0u;
+    const double sky0 = border / (4.0 * W - 4.0);
+    const int i0 = besti / W, j0 = besti - (besti / W) * W;
+
+    // Pass 2: ring sums of f = I - sky0 about the brightest pixel, per half.
+    constexpr int nrings = 45;   // ring_of(2 * (W - 1)^2) + 1
+    unsigned long long* rg = ring + g * kPairRings;
+    const FixedPoint fp((double)amax, sky0, st.npix);
+    for (int r = jl; r < kPairRings; r += W) rg[r] = 0ull;
+    __syncthreads();
+    if (live) {
+      const int dj2 = __mul24(jl - j0, jl - j0);
+#pragma unroll
+      for (int m0 = 0; m0 < kSlots; m0 += 8) {
+        float w8[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w8[q] = v[m0 + q];
+        asm volatile("" : "+v"(w8[0]), "+v"(w8[1]), "+v"(w8[2]), "+v"(w8[3]), "+v"(w8[4]),
+                     "+v"(w8[5]), "+v"(w8[6]), "+v"(w8[7])
+                     :
+                     : "memory");
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int di = m0 + q - i0;
+          fp.deposit(rg, w8[q], __mul24(di, di) + dj2);
+        }
+      }
+    }
+    __syncthreads();
+    // r50 per half: lane j takes rings 3 j .. 3 j + 2 of its stamp
+    long long F;
+    double r50;
+    {
+      const int r0 = 3 * jl;
+      const long long a0 = r0 < nrings ? (long long)rg[r0] : 0;
+      const long long a1 = r0 + 1 < nrings ? (long long)rg[r0 + 1] : 0;
+      const long long a2 = r0 + 2 < nrings ? (long long)rg[r0 + 2] : 0;
+      const long long loc = a0 + a1 + a2;
+      const long long incl = half_scan(loc);
+      F = half_pick(incl, 31, 63);
+      const long long e = incl - loc, c0 = e + a0, c1 = c0 + a1, c2 = c1 + a2;
+      const bool h0 = r0 >= 1 && r0 < nrings && 2 * c0 >= F;
+      const bool h1 = r0 + 1 < nrings && 2 * c1 >= F;
+      const bool h2 = r0 + 2 < nrings && 2 * c2 >= F;
+      const uint64_t m = __ballot(F > 0 && (h0 || h1 || h2));
+      const uint32_t m0 = (uint32_t)m, m1 = (uint32_t)(m >> 32);
+      // (a half with F > 0 crosses at its last ring; the other half's lane
+      // index is then unused)
+      const int L0 = m0 ? __builtin_ctz(m0) : 0, L1 = 32 + (m1 ? __builtin_ctz(m1) : 0);
+      const long long cum = h0 ? c0 : h1 ? c1 : c2, before = h0 ? e : h1 ? c0 : c1;
+      const int r = half_pick(r0 + (h0 ? 0 : h1 ? 1 : 2), L0, L1);
+      const long long cr = half_pick(cum, L0, L1), pr = r == 1 ? 0 : half_pick(before, L0, L1);
+      if (F > 0) {
+        r50 = (r - 1) + (0.5 * (double)F - (double)pr) / (double)(cr - pr);
+      } else {
+        stt |= live ? SHAPE_ST_NONPOSITIVE_FLUX : 0u;
+        r50 = 0.125 * W;
+      }
+    }
+    __syncthreads();  // ring[] is reused by the next pair of stamps
+    const double sigw = weight_sigma(r50, W);
+
+    // Pass 3: centroid iterations from the brightest pixels; a lane sums f wy
+    // and f wy theta2 down its column (as centroid_kernel, one slot per row).
+    double x = j0, y = i0;
+    const float c2 = (float)(kLog2e / (2.0 * sigw * sigw));
+    const float skyf = (float)sky0;
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m) v[m] -= skyf;
+    bool done = !live || !own;
+    int it = 0;
+    for (int step = 0; step < o.max_iter_centroid; ++step) {
+      if (!__any(!done)) break;
+      const float xf = (float)x, yf = (float)y;
+      constexpr int kC = kSlots / 2;
+      wave_sync();  // the previous step's reads of wy_row are done
+      {
+        const float tr = (float)jl - yf;
+        wy_row[lane] = fast_exp2(-(tr * tr) * c2);
+      }
+      wave_sync();
+      float jlf = (float)jl;
+      asm volatile("" : "+v"(jlf));
+      const float t1 = jlf - xf;
+      const float* wy = wy_row + g * W;
+      double s0d = 0.0, s1d = 0.0;
+#pragma unroll
+      for (int m0 = 0; m0 < kSlots; m0 += kColumnBlock) {
+        float b0 = 0.0f, b1 = 0.0f;
+#pragma unroll
+        for (int m = m0; m < m0 + kColumnBlock; ++m) {
+          const float fe = v[m] * wy[m];
+          b0 += fe;
+          b1 = fmaf(fe, (float)(m - kC), b1);
+        }
+        s0d += (double)b0;
+        s1d += (double)b1;
+      }
+      const double wx = (double)fast_exp2(-(t1 * t1) * c2);
+      const double dl = (double)kC - y;
+      double u[4] = {wx * s0d, wx * (double)t1 * s0d, wx * (dl * s0d + s1d), 0.0};
+      half_sum_n(u);
+      if (!done) {
+        ++it;
+        done = centroid_step(u[0], u[1], u[2], x, y, W, o, stt);
+      }
+    }
+    if (live && !(stt & (SHAPE_ST_CONVERGED | SHAPE_ST_NONPOSITIVE_FLUX | SHAPE_ST_LOST)))
+      stt |= SHAPE_ST_MAX_ITER;
+    if (own && jl == 0) {
+      if (live)
+        write_record(out, x, y, sigw, r50, sky0, (double)F / fp.fix, it, stt, iters, status, s);
+    }
+    if (own && !live) write_failed(out, jl, iters, status, s, stt);
+  }
+}
+
 // LDS of the any-side form.
 template <int TEAM>
 struct AnyShared {
@@ -531,7 +714,12 @@ void launch_dtype(const shape_batch& b, const KOpts& o, float* rec, int32_t* ite
     switch (b.side0) {
       case 8: hipLaunchKernelGGL((centroid_kernel<DT, 8>), g, one, 0, stream, b, o, rec, iters, status); break;
       case 16: hipLaunchKernelGGL((centroid_kernel<DT, 16>), g, one, 0, stream, b, o, rec, iters, status); break;
-      case 32: hipLaunchKernelGGL((centroid_kernel<DT, 32>), g, one, 0, stream, b, o, rec, iters, status); break;
+      case 32: {
+        const int64_t n2 = (b.n + 1) / 2;
+        hipLaunchKernelGGL((centroid_pair_kernel<DT>), dim3((unsigned)(n2 < cap ? n2 : cap)), one, 0,
+                           stream, b, o, rec, iters, status);
+        break;
+      }
       default: hipLaunchKernelGGL((centroid_kernel<DT, 64>), g, one, 0, stream, b, o, rec, iters, status);
     }
     return;

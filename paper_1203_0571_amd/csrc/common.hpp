@@ -117,6 +117,12 @@ __device__ inline long long readlane64(long long v, int lane) {
   const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
   return (long long)(((uint64_t)hi << 32) | lo);
 }
+__device__ inline double read_lane_f64(double v, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 __device__ inline bool wave_any(bool p) { return __any(p); }
 
 // Halving steps of a wave reduction: the values a (kept) and b are summed

@@ -342,6 +342,82 @@ __global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_k
   }
 }
 
+// Two 32 x 32 stamps per wave (lanes 32 g + j: column j of stamp g, slot m =
+// row m), as centroid_pair_kernel: the moments and the step of
+// moments_kernel with the sums taken per half-wave, iterating until both
+// stamps stop.
+template <int DT>
+__global__ __launch_bounds__(kWave, SHAPE_MOMENTS_WAVES_PER_SIMD) void moments_pair_kernel(
+    shape_batch b, KOpts o, const float* rec_in, float* rec_out, int32_t* iters,
+    uint32_t* status) {
+  constexpr int W = kPairSide, kSlots = kPairSide;
+  const int lane = threadIdx.x, g = lane >> 5, j = lane & (W - 1);
+  for (int64_t s0 = 2 * (int64_t)blockIdx.x; s0 < b.n; s0 += 2 * (int64_t)gridDim.x) {
+    const int64_t s = s0 + g < b.n ? s0 + g : s0;   // a missing second stamp repeats the first
+    const bool own = s0 + g < b.n;                  // and writes nothing
+    const Stamp st = stamp_info(b, s);
+    float* out = rec_out + s * SHAPE_REC_LEN;
+    float r_in[SHAPE_REC_LEN];
+    const bool rec_ok = read_record(rec_in + s * SHAPE_REC_LEN, r_in);
+    const bool live = !st.bad && rec_ok;
+    float v[kSlots];
+    {
+      const void* sp = stamp_base<DT>(b, st);
+#pragma unroll
+      for (int m = 0; m < kSlots; ++m)
+        v[m] = live ? load_rel<DT>(sp, (uint32_t)(m * W + j), st.scale) : 0.0f;
+    }
+    const double sigw = live ? (double)r_in[SHAPE_REC_SIGW] : 1.0;
+    const float skyf = live ? r_in[SHAPE_REC_SKY0] : 0.0f;
+    const double c = -1.0 / (2.0 * sigw * sigw);           // W' = c W
+    const float cw = (float)(kLog2e / (2.0 * sigw * sigw));
+    StepState z = {live ? (double)r_in[SHAPE_REC_X0] : 0.0, live ? (double)r_in[SHAPE_REC_Y0] : 0.0,
+                   0.0, 0.0, 0.0, 0.0, 0.0, 0u};
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m) v[m] -= skyf;
+    bool done = !live || !own;
+    int it = 0;
+    for (int step = 0; step < o.max_iter_moments; ++step) {
+      if (!__any(!done)) break;
+      constexpr int kC = kSlots / 2;
+      float jl = (float)j;
+      asm volatile("" : "+v"(jl));
+      const float xf = (float)z.x, yf = (float)z.y;
+      const float t1 = jl - xf;
+      const ColumnExp e(z, cw, t1, (float)kC - yf, 1.0f);
+      double T[5] = {};
+      all_blocks<kSlots>(v, e, T, kSlots);
+      double S[5];
+      column_sums(T, (double)kC - z.y, 1.0, S);
+      Mom M = {};
+      add_column(M, (double)jl - z.x, S);
+      double u[12];
+      moments_pack(M, u);
+      half_sum_n(u);
+      if (!done) {
+        ++it;
+        done = moments_step(u, c, W, o, z);
+      }
+    }
+    if (live && !(z.stt & (SHAPE_ST_CONVERGED | SHAPE_ST_NONPOSITIVE_FLUX | SHAPE_ST_SINGULAR |
+                           SHAPE_ST_LOST)))
+      z.stt |= SHAPE_ST_MAX_ITER;
+    const double size = start_size(z, sigw);
+    __syncthreads();  // all lanes have read the input records
+    if (own) {
+      if (live) {
+        if (j == 0) write_out(out, r_in, z, size, it, iters, status, s);
+      } else {
+        if (j < SHAPE_REC_LEN) out[j] = qnan();
+        if (j == 0) {
+          iters[s] = 0;
+          status[s] = st.bad ? st.bad : SHAPE_ST_BAD_INPUT;
+        }
+      }
+    }
+  }
+}
+
 // A team's step state as its leader wave hands it to the others.
 struct StepShare {
   StepState z;
@@ -483,7 +559,12 @@ void launch_dtype(const shape_batch& b, const KOpts& o, const float* rec_in, flo
     switch (b.side0) {
       case 8: hipLaunchKernelGGL((moments_kernel<DT, 8>), g, one, 0, stream, b, o, rec_in, rec_out, iters, status); break;
       case 16: hipLaunchKernelGGL((moments_kernel<DT, 16>), g, one, 0, stream, b, o, rec_in, rec_out, iters, status); break;
-      case 32: hipLaunchKernelGGL((moments_kernel<DT, 32>), g, one, 0, stream, b, o, rec_in, rec_out, iters, status); break;
+      case 32: {
+        const int64_t n2 = (b.n + 1) / 2;
+        hipLaunchKernelGGL((moments_pair_kernel<DT>), dim3((unsigned)(n2 < cap ? n2 : cap)), one, 0,
+                           stream, b, o, rec_in, rec_out, iters, status);
+        break;
+      }
       default: hipLaunchKernelGGL((moments_kernel<DT, 64>), g, one, 0, stream, b, o, rec_in, rec_out, iters, status);
     }
     return;

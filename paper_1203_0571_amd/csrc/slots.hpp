@@ -151,4 +151,70 @@ __device__ __forceinline__ void team_sync() {
     wave_sync();
 }
 
+// Two 32 x 32 stamps per wave: lanes 0-31 hold one stamp, lanes 32-63 the
+// next (group g = lane / 32), lane 32 g + j holding column j, slot m = row m.
+// With 32 pixels per lane instead of 16, each step's reductions and closed
+// forms are shared by two stamps.
+constexpr int kPairSide = 32;
+
+// Sums of N FP64 values (N even) within each half-wave, every lane receiving
+// its half's N totals: v_permlane16_swap halves the values between the rows
+// of a half (rows 0 and 2 then carry entries 0..N/2-1, rows 1 and 3 the
+// rest), a scan within each row of 16 finishes them, and the totals are read
+// from lanes 15, 31 (first half) and 47, 63 (second half).
+template <int N>
+__device__ inline void half_sum_n(double (&u)[N]) {
+  static_assert(N % 2 == 0, "N must be even");
+  constexpr int H = N / 2;
+#pragma unroll
+  for (int j = 0; j < H; ++j) swap_add16(u[j], u[j + H]);
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    u[j] = dpp::add<dpp::kShr1, 0xf>(u[j]);
+    u[j] = dpp::add<dpp::kShr2, 0xf>(u[j]);
+    u[j] = dpp::add<dpp::kShr4, 0xf>(u[j]);
+    u[j] = dpp::add<dpp::kShr8, 0xf>(u[j]);
+  }
+  const bool hi = (threadIdx.x & (kWave - 1)) >= 32;
+  double t[N];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    t[j] = hi ? read_lane_f64(u[j], 47) : read_lane_f64(u[j], 15);
+    t[j + H] = hi ? read_lane_f64(u[j], 63) : read_lane_f64(u[j], 31);
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) u[j] = t[j];
+}
+
+// Inclusive scan of an int64 within each half-wave (row scans, then the last
+// lane of rows 0 and 2 added to rows 1 and 3).
+__device__ inline long long half_scan(long long v) {
+  v = dpp::add<dpp::kShr1, 0xf>(v);
+  v = dpp::add<dpp::kShr2, 0xf>(v);
+  v = dpp::add<dpp::kShr4, 0xf>(v);
+  v = dpp::add<dpp::kShr8, 0xf>(v);
+  v = dpp::add<dpp::kBcast15, 0xa>(v);
+  return v;
+}
+
+// A value as held by lane `l0` for the first half-wave and by lane `l1` for
+// the second (l0, l1 wave-uniform).
+__device__ __forceinline__ long long half_pick(long long v, int l0, int l1) {
+  const bool hi = (threadIdx.x & (kWave - 1)) >= 32;
+  const long long a = readlane64(v, l0), b = readlane64(v, l1);
+  return hi ? b : a;
+}
+__device__ __forceinline__ int half_pick(int v, int l0, int l1) {
+  const bool hi = (threadIdx.x & (kWave - 1)) >= 32;
+  const int a = __builtin_amdgcn_readlane(v, l0), b = __builtin_amdgcn_readlane(v, l1);
+  return hi ? b : a;
+}
+
+// Whether any lane of this lane's half-wave has p set.
+__device__ __forceinline__ bool half_any(bool p) {
+  const uint64_t m = __ballot(p);
+  const bool hi = (threadIdx.x & (kWave - 1)) >= 32;
+  return ((hi ? m >> 32 : m) & 0xffffffffull) != 0;
+}
+
 }  // namespace shape

@@ -36,9 +36,9 @@ if ROOT not in sys.path:
 # + 1 transcendental (a shared factor dm/dR^2, the N u products, eight
 # columns), J^T J 63, J^T r and chi^2 17.
 FLOP_PER_PIXEL_SWEEP = 124.0
-# The hot-path table's planning estimate of the same work: about 85 VALU
-# operations per pixel and sweep, 150 FLOP with FMA = 2.
-FLOP_PER_PIXEL_SWEEP_SURVEY = 150.0
+# An a-priori estimate of the same work, made before the sweep was written:
+# about 85 VALU operations per pixel and sweep, 150 FLOP with FMA = 2.
+FLOP_PER_PIXEL_SWEEP_ESTIMATE = 150.0
 # Per pixel per iteration of the other stages (FMA = 2, transcendental = 1):
 # centroid sweep: offsets 2, R^2 3, weight 2, f W 2, three sums 5 -> 14;
 # moments sweep: offsets 2, products 3, R^2 5, weight 2, f W 2, eleven
@@ -178,7 +178,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(stamps are independent; a shard per GPU would run the same kernels). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
@@ -369,7 +369,7 @@ def main():
     chosen = max(ok or list(results), key=lambda f: results[f]["objs"])
     rc = results[chosen]
     achieved = rc["pixel_sweeps"] * FLOP_PER_PIXEL_SWEEP / (rc["fit_ms"] * 1e-3) / 1e12
-    achieved_s = rc["pixel_sweeps"] * FLOP_PER_PIXEL_SWEEP_SURVEY / (rc["fit_ms"] * 1e-3) / 1e12
+    achieved_s = rc["pixel_sweeps"] * FLOP_PER_PIXEL_SWEEP_ESTIMATE / (rc["fit_ms"] * 1e-3) / 1e12
     wl_desc = ("sersic64h: 262,144 x 64x64 Sersic stamps, seed 0" if wl == "sersic64h" else
                "plain48: 100,000 x 48x48 Sersic stamps, seed 0")
     line = {
@@ -405,10 +405,10 @@ def main():
                      "flop_per_pixel_sweep": FLOP_PER_PIXEL_SWEEP,
                      "flop_count": "the sweep's own formulation, FMA = 2, transcendental = 1",
                      "pixel_sweeps_per_launch": rc["pixel_sweeps"],
-                     "survey_count": {"flop_per_pixel_sweep": FLOP_PER_PIXEL_SWEEP_SURVEY,
+                     "estimate_count": {"flop_per_pixel_sweep": FLOP_PER_PIXEL_SWEEP_ESTIMATE,
                                       "achieved": round(achieved_s, 3),
                                       "frac": round(achieved_s / ALU_PEAK_TFLOPS, 4),
-                                      "note": "the hot-path table's estimate of ~85 VALU ops "
+                                      "note": "an a-priori estimate of ~85 VALU ops "
                                               "per pixel-sweep, FMA = 2"}},
     }
     if cpu:

@@ -169,6 +169,52 @@ def test_edge_cases(shape):
     assert out["p"].shape == (0, 8)
 
 
+def test_two_stamps_per_wave(shape):
+    """Batches of 32 x 32 stamps take two stamps per wave in the register-stamp
+    centroid and moments: a stamp's results do not depend on its partner (bit
+    for bit, against a batch that pairs it differently), a failing stamp
+    leaves its partner alone, and an odd count leaves the last stamp without
+    one.  Statuses agree with the oracle."""
+    rng = np.random.default_rng(11)
+
+    def gal(x, y, e1, e2, re, n, amp):
+        img = synth.render_sersic(32, np.array([x, y, e1, e2, re, n, amp, 10.0]))[0] + 10
+        return img + rng.normal(0, 2.0, img.shape)
+
+    A = gal(15.3, 16.1, 0.2, -0.1, 3.0, 1.5, 600.0)
+    B = gal(14.2, 15.7, -0.3, 0.1, 4.0, 0.8, 400.0)
+    C = gal(16.8, 14.9, 0.05, 0.25, 2.5, 2.5, 900.0)
+    nan = A.copy()
+    nan[3, 9] = np.nan
+    flat = np.full((32, 32), 10.0)
+    # pairs: (A, nan), (B, A with sigma <= 0), (flat, C), (B, -)
+    b1 = _custom_batch([A, nan, B, A, flat, C, B], [2.0, 2.0, 2.0, -1.0, 1.0, 2.0, 2.0])
+    b2 = _custom_batch([C, B, A], [2.0, 2.0, 2.0])
+    o = shape.default_opts()
+    outs = []
+    for b in (b1, b2):
+        db = shape.DeviceBatch.from_host(b, "cuda:0")
+        assert db.side0 == 32 and db.sides is None
+        rec0, it0, st0 = shape.centroid(db, o)
+        rec1, it1, st1 = shape.moments(db, rec0, o)
+        outs.append([x.cpu().numpy() for x in (rec0, it0, st0, rec1, it1, st1)])
+    for i1, i2 in ((0, 2), (2, 1), (5, 0), (6, 1)):
+        for a, c in zip(outs[0], outs[1]):
+            np.testing.assert_array_equal(a[i1], c[i2])
+    st0, st1 = outs[0][2], outs[0][5]
+    assert st0[1] == shape.ST_NONFINITE_INPUT and st0[3] == shape.ST_BAD_INPUT
+    # the moments stage rejects the failed centroid records themselves
+    assert st1[1] == shape.ST_BAD_INPUT and st1[3] == shape.ST_BAD_INPUT
+    assert st0[4] & shape.ST_NONPOSITIVE_FLUX
+    assert np.isnan(outs[0][0][1]).all() and np.isnan(outs[0][3][3]).all()
+    ref = oracle.pipeline(b1, oracle_opts_like(o))
+    np.testing.assert_array_equal(st0, ref["status"][:, 0])
+    good = [0, 2, 5, 6]
+    np.testing.assert_array_equal(st1[good + [4]], ref["status"][good + [4], 1])
+    assert np.abs(outs[0][3][good, :2] - ref["mom"][good, :2]).max() <= BAR_X
+    assert np.abs(outs[0][3][good, 2:4] - ref["mom"][good, 2:4]).max() <= BAR_E
+
+
 def test_every_side_stages(shape):
     """Centroid and moments on one batch holding every side from 4 to 128
     (two stamps each, mixed in order): every register layout of the any-side

@@ -186,6 +186,34 @@ __device__ inline void half_sum_n(double (&u)[N]) {
   for (int j = 0; j < N; ++j) u[j] = t[j];
 }
 
+// The same for N FP32 values.
+template <int N>
+__device__ inline void half_sum_n(float (&u)[N]) {
+  static_assert(N % 2 == 0, "N must be even");
+  constexpr int H = N / 2;
+#pragma unroll
+  for (int j = 0; j < H; ++j) swap_add16(u[j], u[j + H]);
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    u[j] = dpp::add<dpp::kShr1, 0xf>(u[j]);
+    u[j] = dpp::add<dpp::kShr2, 0xf>(u[j]);
+    u[j] = dpp::add<dpp::kShr4, 0xf>(u[j]);
+    u[j] = dpp::add<dpp::kShr8, 0xf>(u[j]);
+  }
+  const bool hi = (threadIdx.x & (kWave - 1)) >= 32;
+  auto rl = [](float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+  };
+  float t[N];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    t[j] = hi ? rl(u[j], 47) : rl(u[j], 15);
+    t[j + H] = hi ? rl(u[j], 63) : rl(u[j], 31);
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) u[j] = t[j];
+}
+
 // Inclusive scan of an int64 within each half-wave (row scans, then the last
 // lane of rows 0 and 2 added to rows 1 and 3).
 __device__ inline long long half_scan(long long v) {

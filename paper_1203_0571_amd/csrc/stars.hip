@@ -17,9 +17,10 @@
 // Only w changes from step to step, so f and R^2 of every pixel are formed
 // once.  One wave per stamp: stamps of up to 64 x kCache pixels keep f and
 // R^2 in registers (pixel lane + 64 q in slot q) and read HBM once; larger
-// stamps recompute them from the stamp on every step.  (Two 32 x 32 stamps per
-// wave, each on a half-wave, ran slower: a wave then iterates as long as the
-// slower of its two stars.)
+// stamps recompute them from the stamp on every step.  A batch of 32 x 32
+// stars in the FP32 instance takes two stars per wave (star_pair_kernel):
+// with FP64 reductions that was slower, since a wave iterates as long as the
+// slower of its two stars; with FP32 ones it gains a little (3-4%).
 //
 // Precision (type T of the sums and of the step's closed forms): with 16
 // pixels per lane the step's reductions and closed forms cost as much as the
@@ -31,6 +32,7 @@
 // a tolerance and the 1e-3 agreement with the FP64 oracle.  Tighter
 // tolerances would stop on that rounding, so they take T = FP64: FP32 runs of
 // 8 pixels carried in FP64, FP64 wave sums and closed forms.
+#include "slots.hpp"
 #include "kernels.hpp"
 
 namespace shape {
@@ -250,12 +252,114 @@ __global__ __launch_bounds__(kWave) void star_kernel(shape_batch b, const float*
   }
 }
 
+// Two 32 x 32 stars per wave for the FP32 instance (lanes 32 g + j hold
+// column j of star g, slot m = row m): each lane sums 32 pixels per step,
+// and the step's reduction and closed forms are shared by the two stars;
+// the wave iterates until both stop.
+template <int DT, int PROFILE>
+__global__ __launch_bounds__(kWave) void star_pair_kernel(shape_batch b, const float* rec,
+                                                          double tol, int max_iter,
+                                                          double beta_fixed, float* out,
+                                                          int32_t* iters, uint32_t* status) {
+  constexpr int W = kPairSide;
+  const int lane = threadIdx.x, g = lane >> 5, j = lane & (W - 1);
+  for (int64_t s0 = 2 * (int64_t)blockIdx.x; s0 < b.n; s0 += 2 * (int64_t)gridDim.x) {
+    const int64_t s = s0 + g < b.n ? s0 + g : s0;   // a missing second star repeats the first
+    const bool own = s0 + g < b.n;                  // and writes nothing
+    const Stamp st = stamp_info(b, s);
+    float r[SHAPE_REC_LEN];
+    bool finite = true;
+#pragma unroll
+    for (int q = 0; q < SHAPE_REC_LEN; ++q) {
+      r[q] = rec[s * SHAPE_REC_LEN + q];
+      finite = finite && (q == SHAPE_REC_SIZE || __builtin_isfinite(r[q]));  // size may be NaN
+    }
+    const bool live = !st.bad && finite;
+    const double g1 = live ? r[SHAPE_REC_E1] : 0.0, g2 = live ? r[SHAPE_REC_E2] : 0.0;
+    StarGeom G;
+    G.x0 = live ? r[SHAPE_REC_X0] : 0.0f;
+    G.y0 = live ? r[SHAPE_REC_Y0] : 0.0f;
+    G.a11 = (float)(1.0 - g1);
+    G.a12 = (float)(-g2);
+    G.a22 = (float)(1.0 + g1);
+    G.invD = (float)(1.0 / (1.0 - g1 * g1 - g2 * g2));
+    G.sky = live ? r[SHAPE_REC_SKY0] : 0.0f;
+    float cf[W], cr[W];
+    {
+      const void* sp = stamp_base<DT>(b, st);
+#pragma unroll
+      for (int m = 0; m < W; ++m) {
+        cf[m] = live ? load_rel<DT>(sp, (uint32_t)(m * W + j), st.scale) - G.sky : 0.0f;
+        cr[m] = star_r2(G, m, j);
+      }
+    }
+    float w = live ? (float)start_width<PROFILE>(r, beta_fixed) : 1.0f;
+    float size = w, beta = PROFILE == 2 ? (float)beta_fixed : 0.0f, r0 = 0.0f, s0_ok = 0.0f;
+    const float tolt = (float)tol;
+    uint32_t stt = 0;
+    int it = 0;
+    bool done = !live || !own;
+    for (int step = 0; step < max_iter; ++step) {
+      if (!__any(!done)) break;
+      const float c = weight_const<PROFILE>(w);
+      float u[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // r0, r2, r4 (and a pad)
+#pragma unroll
+      for (int m = 0; m < W; ++m) star_accumulate<PROFILE>(cf[m], cr[m], c, u);
+      half_sum_n(u);
+      if (!done) {
+        ++it;
+        r0 = u[0];
+        float ns;
+        if (!star_step<PROFILE>(u[0], u[1], u[2], beta, ns, stt)) {
+          done = true;
+        } else {
+          const bool small = fabsf(ns - w) < tolt * ns;   // fractional change below tol
+          size = ns;
+          w = ns;
+          s0_ok = u[0];
+          if (small) {
+            stt |= SHAPE_ST_CONVERGED;
+            done = true;
+          }
+        }
+      }
+    }
+    if (!own) continue;
+    if (!live) {
+      if (j < 4) out[s * 4 + j] = qnan();
+      if (j == 0) {
+        iters[s] = 0;
+        status[s] = st.bad ? st.bad : SHAPE_ST_BAD_INPUT;
+      }
+      continue;
+    }
+    double I0 = 0.0;
+    if (s0_ok > 0.0f)
+      I0 = (PROFILE == 0 ? (double)s0_ok : (double)s0_ok * ((double)beta + 2.0)) /
+           (kPi * (double)size * (double)size);
+    if (!(stt & (SHAPE_ST_CONVERGED | SHAPE_ST_NONPOSITIVE_FLUX | SHAPE_ST_SINGULAR)))
+      stt |= SHAPE_ST_MAX_ITER;
+    if (j == 0) {
+      out[s * 4 + 0] = size;
+      out[s * 4 + 1] = beta;
+      out[s * 4 + 2] = (float)I0;
+      out[s * 4 + 3] = r0;
+      iters[s] = it;
+      status[s] = stt;
+    }
+  }
+}
+
 template <int DT, int PROFILE>
 void launch_one(const shape_batch& b, const float* rec, double tol, int max_iter, double beta,
                 float* out, int32_t* iters, uint32_t* status, hipStream_t stream) {
   const int64_t cap = 1ll << 30;
   const dim3 grid((unsigned)(b.n < cap ? b.n : cap));
-  if (tol >= kStarExactTol)
+  if (tol >= kStarExactTol && !b.side && b.side0 == kPairSide) {
+    const int64_t n2 = (b.n + 1) / 2;
+    hipLaunchKernelGGL((star_pair_kernel<DT, PROFILE>), dim3((unsigned)(n2 < cap ? n2 : cap)),
+                       dim3(kWave), 0, stream, b, rec, tol, max_iter, beta, out, iters, status);
+  } else if (tol >= kStarExactTol)
     hipLaunchKernelGGL((star_kernel<DT, PROFILE, float>), grid, dim3(kWave), 0, stream, b, rec,
                        tol, max_iter, beta, out, iters, status);
   else

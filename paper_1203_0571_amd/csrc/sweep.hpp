@@ -357,7 +357,11 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
   // Sersic instance the constant factors k7 (of the x0, y0, e1, e2 columns)
   // and k4 (of the Re column) are applied to the sums once, after the sweep.
   constexpr bool kFold = sizeof(T) == 4 && MODEL == SHAPE_SERSIC;
-  auto pixel = [&](const T d, T R2, const T n1, const T n2, const T P2, const T P3) {
+  // first: the pixel opens a run of kFlush pixels, so its terms start the
+  // FP32 partials instead of being added to them (the same values as adding
+  // them to zeros; a compile-time constant where the runs are unrolled)
+  auto pixel = [&](const T d, T R2, const T n1, const T n2, const T P2, const T P3,
+                   const bool first = false) {
     const bool floored = R2 < A::kR2Floor;
     R2 = floored ? A::kR2Floor : R2;
     T J[8];
@@ -398,14 +402,14 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     J[7] = (T)1;
     const double rd = (double)r;
     if constexpr (kFlush > 0)
-      c2p = A::fma(r, r, c2p);
+      c2p = first ? r * r : A::fma(r, r, c2p);
     else
       acc.c2 = fma(rd, rd, acc.c2);
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       if (!has(EM, a)) continue;
       if constexpr (kFlush > 0)
-        gp[a] = (a == 7) ? gp[a] + r : A::fma(J[a], r, gp[a]);
+        gp[a] = (a == 7) ? (first ? r : gp[a] + r) : (first ? J[a] * r : A::fma(J[a], r, gp[a]));
       else
         acc.g[a] = (a == 7) ? acc.g[a] + rd : fma((double)J[a], rd, acc.g[a]);
       if constexpr (JTJ) {
@@ -437,15 +441,42 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     const int nstep = st.npix / kWave;
     const void* sp = stamp_base<DT>(b, st);
     uint32_t k = (uint32_t)lane;
+    bool blocked = false;
+    if constexpr (kFlush > 0) {
+      // FP32 stamps in memory, whole runs of kFlush rows (sides 32 and 64):
+      // the run is unrolled, so its loads issue together and its first pixel
+      // opens the partials (2 fewer VALU per pixel); measured on 262,144 64 x 64
+      // stamps: fit 23.1 -> 20.8 ms, 32 x 32 4-parameter fit 3.72 -> 2.83 ms.
+      // FP16 stamps staged in LDS ran 5% slower unrolled and keep the loop.
+      blocked = DT == SHAPE_F32 && nstep % kFlush == 0;   // wave-uniform
+      if (blocked) {
 #pragma unroll 1
-    for (int m = 0; m < nstep; ++m) {
-      const T d = (T)load_rel<DT>(sp, k, st.scale);
-      pixel(d, A::fma(A::fma(t.qa, u2, qb), u2, qc), A::fma(t.n12, u2, c3), A::fma(t.n22, u2, c4),
-            A::fma(A::fma(t.p2a, u2, p2b), u2, p2c), A::fma(A::fma(t.p3a, u2, p3b), u2, p3c));
-      u2 += di;
-      k += kWave;
-      if constexpr (kFlush > 0)
-        if (m % kFlush == kFlush - 1) flush();   // m is wave-uniform
+        for (int m0 = 0; m0 < nstep; m0 += kFlush) {
+#pragma unroll
+          for (int q = 0; q < kFlush; ++q) {
+            const T d = (T)load_rel<DT>(sp, k + (uint32_t)(q * kWave), st.scale);
+            pixel(d, A::fma(A::fma(t.qa, u2, qb), u2, qc), A::fma(t.n12, u2, c3),
+                  A::fma(t.n22, u2, c4), A::fma(A::fma(t.p2a, u2, p2b), u2, p2c),
+                  A::fma(A::fma(t.p3a, u2, p3b), u2, p3c), q == 0);
+            u2 += di;
+          }
+          k += (uint32_t)(kFlush * kWave);
+          flush();
+        }
+      }
+    }
+    if (!blocked) {
+#pragma unroll 1
+      for (int m = 0; m < nstep; ++m) {
+        const T d = (T)load_rel<DT>(sp, k, st.scale);
+        pixel(d, A::fma(A::fma(t.qa, u2, qb), u2, qc), A::fma(t.n12, u2, c3),
+              A::fma(t.n22, u2, c4), A::fma(A::fma(t.p2a, u2, p2b), u2, p2c),
+              A::fma(A::fma(t.p3a, u2, p3b), u2, p3c));
+        u2 += di;
+        k += kWave;
+        if constexpr (kFlush > 0)
+          if (m % kFlush == kFlush - 1) flush();   // m is wave-uniform
+      }
     }
   } else {
     // the lane-stride walk (any side, any team), directly or through LDS

@@ -441,28 +441,32 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     const int nstep = st.npix / kWave;
     const void* sp = stamp_base<DT>(b, st);
     uint32_t k = (uint32_t)lane;
-    bool blocked = false;
-    if constexpr (kFlush > 0) {
-      // FP32 stamps in memory, whole runs of kFlush rows (sides 32 and 64):
-      // the run is unrolled, so its loads issue together and its first pixel
-      // opens the partials (2 fewer VALU per pixel); measured on 262,144 64 x 64
-      // stamps: fit 23.1 -> 20.8 ms, 32 x 32 4-parameter fit 3.72 -> 2.83 ms.
-      // FP16 stamps staged in LDS ran 5% slower unrolled and keep the loop.
-      blocked = DT == SHAPE_F32 && nstep % kFlush == 0;   // wave-uniform
-      if (blocked) {
+    // FP32 stamps in memory, whole runs of kRun rows (sides 32 and 64): the
+    // run is unrolled, so its loads issue together, and in the FP32 instance
+    // its first pixel opens the partials (2 fewer VALU per pixel); measured
+    // on 262,144 64 x 64 stamps: fit 23.1 -> 20.8 ms, 32 x 32 4-parameter fit
+    // 3.72 -> 2.83 ms; FP64 chi^2 0.74 -> 0.72 ms, with J^T J 1.47 -> 1.33 ms
+    // (65,536 stamps).  FP16 stamps staged in LDS ran 5% slower unrolled and
+    // keep the loop, as does the FP64 gradient without J^T J, whose five waves
+    // per SIMD leave the unrolled run too few registers (136 spilled, 4x
+    // slower).
+    constexpr int kRun = 8;
+    static_assert(kFlush == 0 || kFlush == kRun, "a run is one partial-sum block");
+    constexpr bool kUnroll = DT == SHAPE_F32 && (sizeof(T) == 4 || EM == 0u || JTJ);
+    const bool blocked = kUnroll && nstep % kRun == 0;   // wave-uniform
+    if (blocked) {
 #pragma unroll 1
-        for (int m0 = 0; m0 < nstep; m0 += kFlush) {
+      for (int m0 = 0; m0 < nstep; m0 += kRun) {
 #pragma unroll
-          for (int q = 0; q < kFlush; ++q) {
-            const T d = (T)load_rel<DT>(sp, k + (uint32_t)(q * kWave), st.scale);
-            pixel(d, A::fma(A::fma(t.qa, u2, qb), u2, qc), A::fma(t.n12, u2, c3),
-                  A::fma(t.n22, u2, c4), A::fma(A::fma(t.p2a, u2, p2b), u2, p2c),
-                  A::fma(A::fma(t.p3a, u2, p3b), u2, p3c), q == 0);
-            u2 += di;
-          }
-          k += (uint32_t)(kFlush * kWave);
-          flush();
+        for (int q = 0; q < kRun; ++q) {
+          const T d = (T)load_rel<DT>(sp, k + (uint32_t)(q * kWave), st.scale);
+          pixel(d, A::fma(A::fma(t.qa, u2, qb), u2, qc), A::fma(t.n12, u2, c3),
+                A::fma(t.n22, u2, c4), A::fma(A::fma(t.p2a, u2, p2b), u2, p2c),
+                A::fma(A::fma(t.p3a, u2, p3b), u2, p3c), q == 0);
+          u2 += di;
         }
+        k += (uint32_t)(kRun * kWave);
+        flush();
       }
     }
     if (!blocked) {

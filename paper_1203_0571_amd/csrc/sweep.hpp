@@ -340,23 +340,52 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
   T c2p = (T)0, gp[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) gp[k] = (T)0;
+  // For the FP32 Sersic instance the constant factors k7 (of the x0, y0, e1,
+  // e2 columns) and k4 (of the Re column) are applied to the sums once, after
+  // the sweep.
+  constexpr bool kFold = sizeof(T) == 4 && MODEL == SHAPE_SERSIC;
+  // Moment form of the row layout (FP32 Sersic with x0, y0, e1, e2 free):
+  // along a lane's column the four shape columns are h times polynomials in
+  // u2 of degree 1, 1, 2, 2 with per-column coefficients, J_k = sum_j C_kj
+  // h u2^j.  The lane therefore sums H_j = h u2^j (j = 0..2) against the
+  // other quantities instead of the four columns: M_s = sum h^2 u2^s
+  // (s = 0..4) for the 4 x 4 block, sum H_j v for v = J_Re, J_n, J_I0, 1 and
+  // r, and forms the column sums from them once per sweep -- 22 VALU
+  // operations per pixel where the columns cost 40.
+  constexpr bool kMom = kFold && JTJ && LAYOUT == kLayoutRows && (EM & 0xFu) == 0xFu;
+  constexpr int kMomN = kMom ? 3 : 1;
+  T mM[2 * kMomN - 1], mX[3][kMomN], mY[kMomN], gq[kMomN];
+  double gm[kMomN];
+#pragma unroll
+  for (int j = 0; j < kMomN; ++j) {
+    mY[j] = gq[j] = (T)0;
+    gm[j] = 0.0;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) mX[v][j] = (T)0;
+  }
+#pragma unroll
+  for (int s = 0; s < 2 * kMomN - 1; ++s) mM[s] = (T)0;
   auto flush = [&]() {
     if constexpr (kFlush > 0) {
       acc.c2 += (double)c2p;
       c2p = (T)0;
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
-        if (!has(EM, a)) continue;
+        if (!has(EM, a) || (kMom && a < 4)) continue;
         acc.g[a] += (double)gp[a];
         gp[a] = (T)0;
+      }
+      if constexpr (kMom) {
+#pragma unroll
+        for (int j = 0; j < kMomN; ++j) {
+          gm[j] += (double)gq[j];
+          gq[j] = (T)0;
+        }
       }
     }
   };
   // Per pixel: d = data, R2 = R^2 (unfloored), (n1, n2) = N u and the
-  // e-derivative factors P2 = e1 R^2 + w_1, P3 = e2 R^2 + w_2.  For the FP32
-  // Sersic instance the constant factors k7 (of the x0, y0, e1, e2 columns)
-  // and k4 (of the Re column) are applied to the sums once, after the sweep.
-  constexpr bool kFold = sizeof(T) == 4 && MODEL == SHAPE_SERSIC;
+  // e-derivative factors P2 = e1 R^2 + w_1, P3 = e2 R^2 + w_2.
   // first: the pixel opens a run of kFlush pixels, so its terms start the
   // FP32 partials instead of being added to them (the same values as adding
   // them to zeros; a compile-time constant where the runs are unrolled)
@@ -425,6 +454,56 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
       }
     }
   };
+  // The moment form's pixel (kMom): the Sersic render as in pixel(), then the
+  // H_j sums; the Re, n, I0 and sky columns are summed among themselves as
+  // there.
+  auto mom_pixel = [&](const T d, const T u2, T R2, const bool first) {
+    const bool floored = R2 < A::kR2Floor;
+    R2 = floored ? A::kR2Floor : R2;
+    const T L = A::lg2(R2);
+    const T tt = A::ex2(A::fma(L, t.ha, t.hc));
+    const T m0 = A::ex2(t.nb2 * tt);
+    const T c = m0 * tt;
+    T h = c * A::rcp(R2);
+    h = floored ? (T)0 : h;
+    T J[8];
+    J[4] = c;
+    if constexpr (has(EM, 5)) J[5] = c * A::fma(L, t.k5a, t.k5b);
+    J[6] = m0;
+    J[7] = (T)1;
+    const T r = d - A::fma(t.I0, m0, t.sky);
+    T H[kMomN];
+    H[0] = h;
+#pragma unroll
+    for (int j = 1; j < kMomN; ++j) H[j] = H[j - 1] * u2;
+    c2p = first ? r * r : A::fma(r, r, c2p);
+#pragma unroll
+    for (int j = 0; j < kMomN; ++j) gq[j] = first ? H[j] * r : A::fma(H[j], r, gq[j]);
+#pragma unroll
+    for (int s = 0; s < 2 * kMomN - 1; ++s) {
+      const int i = s < kMomN ? s : kMomN - 1, j = s - i;   // H_i H_j, i + j = s
+      mM[s] = A::fma(H[i], H[j], mM[s]);
+    }
+#pragma unroll
+    for (int a = 4; a < 8; ++a) {
+      if (!has(EM, a)) continue;
+      gp[a] = (a == 7) ? (first ? r : gp[a] + r) : (first ? J[a] * r : A::fma(J[a], r, gp[a]));
+#pragma unroll
+      for (int j = 0; j < kMomN; ++j)
+        if (a == 7)
+          mY[j] += H[j];
+        else
+          mX[a - 4][j] = A::fma(H[j], J[a], mX[a - 4][j]);
+#pragma unroll
+      for (int c2 = a; c2 < 8; ++c2) {
+        if (!has(EM, c2) || (c2 == 7 && a == 7)) continue;
+        if (c2 == 7)
+          acc.A[tri(a, c2)] += J[a];
+        else
+          acc.A[tri(a, c2)] = A::fma(J[a], J[c2], acc.A[tri(a, c2)]);
+      }
+    }
+  };
   if constexpr (LAYOUT == kLayoutRows) {
     static_assert(STRIDE == kWave, "the row layout is for a wave alone on its stamp");
     const int lane = tid < 0 ? (int)(threadIdx.x & (kWave - 1)) : tid;
@@ -454,15 +533,21 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     static_assert(kFlush == 0 || kFlush == kRun, "a run is one partial-sum block");
     constexpr bool kUnroll = DT == SHAPE_F32 && (sizeof(T) == 4 || EM == 0u || JTJ);
     const bool blocked = kUnroll && nstep % kRun == 0;   // wave-uniform
+    auto row_pixel = [&](const T d, const T u2, const bool first) {
+      const T R2 = A::fma(A::fma(t.qa, u2, qb), u2, qc);
+      if constexpr (kMom)
+        mom_pixel(d, u2, R2, first);
+      else
+        pixel(d, R2, A::fma(t.n12, u2, c3), A::fma(t.n22, u2, c4),
+              A::fma(A::fma(t.p2a, u2, p2b), u2, p2c), A::fma(A::fma(t.p3a, u2, p3b), u2, p3c),
+              first);
+    };
     if (blocked) {
 #pragma unroll 1
       for (int m0 = 0; m0 < nstep; m0 += kRun) {
 #pragma unroll
         for (int q = 0; q < kRun; ++q) {
-          const T d = (T)load_rel<DT>(sp, k + (uint32_t)(q * kWave), st.scale);
-          pixel(d, A::fma(A::fma(t.qa, u2, qb), u2, qc), A::fma(t.n12, u2, c3),
-                A::fma(t.n22, u2, c4), A::fma(A::fma(t.p2a, u2, p2b), u2, p2c),
-                A::fma(A::fma(t.p3a, u2, p3b), u2, p3c), q == 0);
+          row_pixel((T)load_rel<DT>(sp, k + (uint32_t)(q * kWave), st.scale), u2, q == 0);
           u2 += di;
         }
         k += (uint32_t)(kRun * kWave);
@@ -472,14 +557,56 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     if (!blocked) {
 #pragma unroll 1
       for (int m = 0; m < nstep; ++m) {
-        const T d = (T)load_rel<DT>(sp, k, st.scale);
-        pixel(d, A::fma(A::fma(t.qa, u2, qb), u2, qc), A::fma(t.n12, u2, c3),
-              A::fma(t.n22, u2, c4), A::fma(A::fma(t.p2a, u2, p2b), u2, p2c),
-              A::fma(A::fma(t.p3a, u2, p3b), u2, p3c));
+        row_pixel((T)load_rel<DT>(sp, k, st.scale), u2, false);
         u2 += di;
         k += kWave;
         if constexpr (kFlush > 0)
           if (m % kFlush == kFlush - 1) flush();   // m is wave-uniform
+      }
+    }
+    if constexpr (kMom) {
+      // the column sums from the moments, per lane, in FP64: column k is
+      // h sum_j C[k][j] u2^j (degree 1 for x0, y0, 2 for e1, e2)
+      flush();
+      const double C[4][3] = {{(double)c3, (double)t.n12, 0.0},
+                              {(double)c4, (double)t.n22, 0.0},
+                              {(double)p2c, (double)p2b, (double)t.p2a},
+                              {(double)p3c, (double)p3b, (double)t.p3a}};
+      double M[5], X[3][3], Y[3];
+#pragma unroll
+      for (int s = 0; s < 5; ++s) M[s] = (double)mM[s];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        Y[j] = (double)mY[j];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) X[v][j] = (double)mX[v][j];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int da = a < 2 ? 2 : 3;   // coefficients of column a
+        double g = 0.0, y = 0.0, x[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < da; ++j) {
+          g = fma(C[a][j], gm[j], g);
+          y = fma(C[a][j], Y[j], y);
+#pragma unroll
+          for (int v = 0; v < 3; ++v) x[v] = fma(C[a][j], X[v][j], x[v]);
+        }
+        acc.g[a] = g;
+        if (has(EM, 7)) acc.A[tri(a, 7)] = (T)y;
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+          if (has(EM, 4 + v)) acc.A[tri(a, 4 + v)] = (T)x[v];
+#pragma unroll
+        for (int c2 = a; c2 < 4; ++c2) {
+          const int dc = c2 < 2 ? 2 : 3;
+          double q = 0.0;
+#pragma unroll
+          for (int i = 0; i < da; ++i)
+#pragma unroll
+            for (int j = 0; j < dc; ++j) q = fma(C[a][i] * C[c2][j], M[i + j], q);
+          acc.A[tri(a, c2)] = (T)q;
+        }
       }
     }
   } else {

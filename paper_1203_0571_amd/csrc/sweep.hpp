@@ -320,6 +320,9 @@ inline int single_wave_layout(const shape_batch& b, int model) {
 // Pixels of a lane whose chi^2 and J^T r terms the FP32 instance sums in FP32
 // before carrying the partial sum on in FP64 (0: every term in FP64).  A
 // partial of 8 terms rounds by about as much as the FP32 terms themselves.
+#ifndef SHAPE_ROWS_PEEL
+#define SHAPE_ROWS_PEEL 1
+#endif
 #ifndef SHAPE_SWEEP_FLUSH
 #define SHAPE_SWEEP_FLUSH 8
 #endif
@@ -456,19 +459,32 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
   };
   // The moment form's pixel (kMom): the Sersic render as in pixel(), then the
   // H_j sums; the Re, n, I0 and sky columns are summed among themselves as
-  // there.
-  auto mom_pixel = [&](const T d, const T u2, T R2, const bool first) {
-    const bool floored = R2 < A::kR2Floor;
-    R2 = floored ? A::kR2Floor : R2;
-    const T L = A::lg2(R2);
-    const T tt = A::ex2(A::fma(L, t.ha, t.hc));
+  // there.  It takes R^2 in units of Re^2, s = R^2 S with S = 1 / Re^2
+  // (2^(hc / ha)): then t = 2^(ha log2 s) needs no added constant, and
+  // t / R^2 = S 2^((ha - 1) log2 s) gives h without a reciprocal (one
+  // transcendental fewer per pixel; S goes into the folded factor of the
+  // x0, y0, e1, e2 columns, log2 S into the n column's constant).
+  T mS = (T)1, mFloor = A::kR2Floor, mHam1 = (T)0, mK5b = (T)0;
+  if constexpr (kMom) {
+    const T lS = A::uni(t.hc * A::rcp(t.ha));
+    mS = A::uni(A::ex2(lS));
+    mFloor = A::uni(A::kR2Floor * mS);
+    mHam1 = A::uni(t.ha - (T)1);
+    mK5b = A::uni(A::fma(-lS, t.k5a, t.k5b));
+  }
+  auto mom_pixel = [&](const T d, const T u2, T s2, const bool first) {
+    const bool floored = s2 < mFloor;
+    s2 = floored ? mFloor : s2;
+    const T L = A::lg2(s2);
+    const T tr = A::ex2(L * mHam1);   // t / s
+    const T tt = tr * s2;
     const T m0 = A::ex2(t.nb2 * tt);
     const T c = m0 * tt;
-    T h = c * A::rcp(R2);
+    T h = m0 * tr;                      // h / S
     h = floored ? (T)0 : h;
     T J[8];
     J[4] = c;
-    if constexpr (has(EM, 5)) J[5] = c * A::fma(L, t.k5a, t.k5b);
+    if constexpr (has(EM, 5)) J[5] = c * A::fma(L, t.k5a, mK5b);
     J[6] = m0;
     J[7] = (T)1;
     const T r = d - A::fma(t.I0, m0, t.sky);
@@ -525,22 +541,23 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     // its first pixel opens the partials (2 fewer VALU per pixel); measured
     // on 262,144 64 x 64 stamps: fit 23.1 -> 20.8 ms, 32 x 32 4-parameter fit
     // 3.72 -> 2.83 ms; FP64 chi^2 0.74 -> 0.72 ms, with J^T J 1.47 -> 1.33 ms
-    // (65,536 stamps).  FP16 stamps staged in LDS ran 5% slower unrolled and
-    // keep the loop, as does the FP64 gradient without J^T J, whose five waves
+    // (65,536 stamps).  FP16 stamps staged in LDS ran 5% slower unrolled (4%
+    // in the moment form: 18.1 vs 17.5 ms) and keep the loop, as does the FP64 gradient without J^T J, whose five waves
     // per SIMD leave the unrolled run too few registers (136 spilled, 4x
     // slower).
     constexpr int kRun = 8;
     static_assert(kFlush == 0 || kFlush == kRun, "a run is one partial-sum block");
     constexpr bool kUnroll = DT == SHAPE_F32 && (sizeof(T) == 4 || EM == 0u || JTJ);
     const bool blocked = kUnroll && nstep % kRun == 0;   // wave-uniform
+    // R^2 S along the column (the moment form's units)
+    const T qas = A::uni(t.qa * mS), qbs = qb * mS, qcs = qc * mS;
     auto row_pixel = [&](const T d, const T u2, const bool first) {
-      const T R2 = A::fma(A::fma(t.qa, u2, qb), u2, qc);
       if constexpr (kMom)
-        mom_pixel(d, u2, R2, first);
+        mom_pixel(d, u2, A::fma(A::fma(qas, u2, qbs), u2, qcs), first);
       else
-        pixel(d, R2, A::fma(t.n12, u2, c3), A::fma(t.n22, u2, c4),
-              A::fma(A::fma(t.p2a, u2, p2b), u2, p2c), A::fma(A::fma(t.p3a, u2, p3b), u2, p3c),
-              first);
+        pixel(d, A::fma(A::fma(t.qa, u2, qb), u2, qc), A::fma(t.n12, u2, c3),
+              A::fma(t.n22, u2, c4), A::fma(A::fma(t.p2a, u2, p2b), u2, p2c),
+              A::fma(A::fma(t.p3a, u2, p3b), u2, p3c), first);
     };
     if (blocked) {
 #pragma unroll 1
@@ -554,7 +571,26 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
         flush();
       }
     }
-    if (!blocked) {
+    // The moment form's loop in runs of kRun rows with the run's first pixel
+    // peeled: it opens the FP32 partials, so a flush needs no zeroing.
+    constexpr bool kPeel = SHAPE_ROWS_PEEL && kMom && kFlush == kRun;
+    const bool peeled = kPeel && !blocked && nstep % kRun == 0;   // wave-uniform
+    if (peeled) {
+#pragma unroll 1
+      for (int m0 = 0; m0 < nstep; m0 += kRun) {
+        row_pixel((T)load_rel<DT>(sp, k, st.scale), u2, true);
+        u2 += di;
+        k += kWave;
+#pragma unroll 1
+        for (int q = 1; q < kRun; ++q) {
+          row_pixel((T)load_rel<DT>(sp, k, st.scale), u2, false);
+          u2 += di;
+          k += kWave;
+        }
+        flush();
+      }
+    }
+    if (!blocked && !peeled) {
 #pragma unroll 1
       for (int m = 0; m < nstep; ++m) {
         row_pixel((T)load_rel<DT>(sp, k, st.scale), u2, false);
@@ -597,14 +633,28 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
 #pragma unroll
         for (int v = 0; v < 3; ++v)
           if (has(EM, 4 + v)) acc.A[tri(a, 4 + v)] = (T)x[v];
+      }
+      // P[c][i] = sum_j C[c][j] M[i + j]; entry (a, c) = sum_i C[a][i] P[c][i]
+      double P[4][3];
 #pragma unroll
-        for (int c2 = a; c2 < 4; ++c2) {
-          const int dc = c2 < 2 ? 2 : 3;
+      for (int c2 = 0; c2 < 4; ++c2) {
+        const int dc = c2 < 2 ? 2 : 3;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
           double q = 0.0;
 #pragma unroll
-          for (int i = 0; i < da; ++i)
+          for (int j = 0; j < dc; ++j) q = fma(C[c2][j], M[i + j], q);
+          P[c2][i] = q;
+        }
+      }
 #pragma unroll
-            for (int j = 0; j < dc; ++j) q = fma(C[a][i] * C[c2][j], M[i + j], q);
+      for (int a = 0; a < 4; ++a) {
+        const int da = a < 2 ? 2 : 3;
+#pragma unroll
+        for (int c2 = a; c2 < 4; ++c2) {
+          double q = 0.0;
+#pragma unroll
+          for (int i = 0; i < da; ++i) q = fma(C[a][i], P[c2][i], q);
           acc.A[tri(a, c2)] = (T)q;
         }
       }
@@ -720,7 +770,8 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
   flush();
   if constexpr (kFold) {
     // the folded constant factors: column a of J is s_a times what was summed
-    const T sc[8] = {t.k7, t.k7, t.k7, t.k7, t.k4, (T)1, (T)1, (T)1};
+    const T k7 = kMom ? t.k7 * mS : t.k7;   // the moment form's h is h / S
+    const T sc[8] = {k7, k7, k7, k7, t.k4, (T)1, (T)1, (T)1};
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
       if (!has(EM, a)) continue;

@@ -41,7 +41,10 @@ ALT_CHI2_SLACK = 1e-6
 ALT_NEWTON_SIGMA = 1e-2
 # relative accuracy of the library's FP32 J^T J entries against
 # sqrt(A_ii A_jj): FP32-rounded Jacobian products summed in FP32 over at most
-# 256 pixels per lane, then reduced (a bound, about 25x the largest error seen)
+# 256 pixels per lane, then reduced (about 25x the largest error seen), or,
+# in the row layout's moment form, FP32 moments of h u2^j combined per lane
+# column (an FP32 emulation on 200 random 64 x 64 galaxies: 1.4e-7 at the
+# median, up to 9e-6 on compact, strongly elliptical ones)
 JTJ_EPS = 1e-5
 
 

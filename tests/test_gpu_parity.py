@@ -77,6 +77,34 @@ def test_sersic_workloads_8_params(shape, workload, count):
     check_fit(r, 0.85)
 
 
+@pytest.mark.parametrize("side", [16, 32])
+def test_row_layout_8_params_small_sides(shape, side):
+    """Uniform batches of side 16 and 32 with all eight parameters free take
+    the row layout's moment form (the shape columns summed as moments of
+    h u2^j per lane column) at 4 and 16 rows per lane: the fit's parity rule
+    against the oracle, Sersic galaxies of Re ~ side/8 (Sec. 4.1 recipe)."""
+    rng = np.random.default_rng(100 + side)
+    stamps, sig = [], []
+    for k in range(256):
+        c = (side - 1) / 2.0 + rng.uniform(-1.0, 1.0, 2)
+        e = np.clip(rng.normal(0.0, 0.25, 2), -0.45, 0.45)
+        re = side / 8.0 * np.exp(rng.uniform(-0.3, 0.3))
+        p = np.array([c[0], c[1], e[0], e[1], re, rng.uniform(0.5, 4.0), 0.0, 10.0])
+        prof = synth.render_sersic(side, np.concatenate([p[:6], [1.0, 0.0]]))[0]
+        flux = np.exp(rng.uniform(np.log(2e3), np.log(2e4)))
+        img = prof * (flux / prof.sum()) + 10.0
+        s_ = float(np.sqrt(img.max() - 10.0) / 8.0 + 1.0)
+        stamps.append(img + rng.normal(0.0, s_, img.shape))
+        sig.append(s_)
+    b = _custom_batch(stamps, sig)
+    o = shape.default_opts()
+    g = run_gpu(shape, b, o)
+    ref = oracle.pipeline(b, oracle_opts_like(o, tol_lm=1e-9, max_iter_lm=200))
+    r = compare(g, ref, 0xFF, "sersic%d" % side, batch=b)
+    _check_stages(r)
+    check_fit(r, 0.8)
+
+
 def test_standard_error_stop_only_adds_convergence(shape):
     """The stop on steps below tol_sigma standard errors is an extra way to
     converge: every stamp that converges without it converges with it (the

@@ -44,6 +44,14 @@ FLOP_PER_PIXEL_SWEEP = 124.0
 # -> 82 (the per-lane recombination once per sweep is not counted, as the
 # reduction is not).
 FLOP_PER_PIXEL_SWEEP_MOMENT = 82.0
+# The adjoint's FP64 sweeps in the moment form (64 x 64 stamps): chi^2 and the
+# gradient only -- R^2 4, profile 7 with 3 transcendentals, h (reciprocal and
+# k7) 3, Re and n columns 4, residual 3, H_j 2, chi^2 2, the gradient sums 13,
+# the row step 1 -> 39 (61 for the direct columns: the 124 above without
+# J^T J); with J^T J as well (the LM's normal matrix) 86.
+FLOP_PER_PIXEL_GRAD_MOMENT = 39.0
+FLOP_PER_PIXEL_GRAD_DIRECT = 61.0
+FLOP_PER_PIXEL_GRAD_JTJ_MOMENT = 86.0
 # An a-priori estimate of the same work, made before the sweep was written:
 # about 85 VALU operations per pixel and sweep, 150 FLOP with FMA = 2.
 FLOP_PER_PIXEL_SWEEP_ESTIMATE = 150.0
@@ -811,10 +819,12 @@ def bench_adjoint(args):
     el = time.perf_counter() - t0
     log("adjoint: %s ms per launch; autograd forward+backward %.3f ms"
         % ({k: round(v, 3) for k, v in ms.items()}, el / args.steps * 1e3))
-    # the algorithm's 124 FLOP per pixel (transcendentals counted once, as in
-    # the fit) against the FP64 vector peak: the series for log2 / exp2 are
-    # what this instance spends beyond them
-    achieved = b.n * 64 * 64 * FLOP_PER_PIXEL_SWEEP / (ms["backward"] * 1e-3) / 1e12
+    # the backward's algorithmic FLOP per pixel (chi^2 and the gradient in the
+    # moment form, transcendentals counted once, as in the fit) against the
+    # FP64 vector peak: the FP64 series for log2 / exp2 and the reciprocal's
+    # Newton steps are what this instance spends beyond them
+    rate = lambda f, k: b.n * 64 * 64 * f / (ms[k] * 1e-3) / 1e12
+    achieved = rate(FLOP_PER_PIXEL_GRAD_MOMENT, "backward")
     line = {"metric": "chi^2 gradients/sec (64x64 Sersic stamps, adjoint)",
             "value": round(b.n * args.steps / el, 1), "unit": "gradients/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup,
@@ -826,7 +836,18 @@ def bench_adjoint(args):
             "roofline": {"bound": "alu", "kernel": "chi2 backward (FP64)",
                          "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                         "traffic": None, "launch_ms": round(ms["backward"], 4)}}
+                         "traffic": None, "launch_ms": round(ms["backward"], 4),
+                         "flop_per_pixel": FLOP_PER_PIXEL_GRAD_MOMENT,
+                         "flop_count": "chi^2 and J^T r in the moment form, FMA = 2, "
+                                       "transcendental = 1 (61 for the direct columns: frac %.4f)"
+                                       % (rate(FLOP_PER_PIXEL_GRAD_DIRECT, "backward")
+                                          / ALU_PEAK_TFLOPS),
+                         "jtj_instance": {"flop_per_pixel": FLOP_PER_PIXEL_GRAD_JTJ_MOMENT,
+                                          "launch_ms": round(ms["backward_jtj"], 4),
+                                          "achieved": round(rate(FLOP_PER_PIXEL_GRAD_JTJ_MOMENT,
+                                                                 "backward_jtj"), 3),
+                                          "frac": round(rate(FLOP_PER_PIXEL_GRAD_JTJ_MOMENT,
+                                                             "backward_jtj") / ALU_PEAK_TFLOPS, 4)}}}
     if not args.no_cpu:
         import oracle
         m = min(2048, b.n)

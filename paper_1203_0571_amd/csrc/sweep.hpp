@@ -347,7 +347,8 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
   // e2 columns) and k4 (of the Re column) are applied to the sums once, after
   // the sweep.
   constexpr bool kFold = sizeof(T) == 4 && MODEL == SHAPE_SERSIC;
-  // Moment form of the row layout (FP32 Sersic with x0, y0, e1, e2 free):
+  // Moment form of the row layout (Sersic with x0, y0, e1, e2 free; the FP32
+  // instance of the fit and the FP64 instance of the adjoint):
   // along a lane's column the four shape columns are h times polynomials in
   // u2 of degree 1, 1, 2, 2 with per-column coefficients, J_k = sum_j C_kj
   // h u2^j.  The lane therefore sums H_j = h u2^j (j = 0..2) against the
@@ -355,7 +356,8 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
   // (s = 0..4) for the 4 x 4 block, sum H_j v for v = J_Re, J_n, J_I0, 1 and
   // r, and forms the column sums from them once per sweep -- 22 VALU
   // operations per pixel where the columns cost 40.
-  constexpr bool kMom = kFold && JTJ && LAYOUT == kLayoutRows && (EM & 0xFu) == 0xFu;
+  constexpr bool kMom = MODEL == SHAPE_SERSIC && LAYOUT == kLayoutRows && (EM & 0xFu) == 0xFu &&
+                        (sizeof(T) == 8 || JTJ);
   constexpr int kMomN = kMom ? 3 : 1;
   T mM[2 * kMomN - 1], mX[3][kMomN], mY[kMomN], gq[kMomN];
   double gm[kMomN];
@@ -459,13 +461,17 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
   };
   // The moment form's pixel (kMom): the Sersic render as in pixel(), then the
   // H_j sums; the Re, n, I0 and sky columns are summed among themselves as
-  // there.  It takes R^2 in units of Re^2, s = R^2 S with S = 1 / Re^2
-  // (2^(hc / ha)): then t = 2^(ha log2 s) needs no added constant, and
-  // t / R^2 = S 2^((ha - 1) log2 s) gives h without a reciprocal (one
-  // transcendental fewer per pixel; S goes into the folded factor of the
-  // x0, y0, e1, e2 columns, log2 S into the n column's constant).
+  // there.  The FP32 instance takes R^2 in units of Re^2, s = R^2 S with
+  // S = 1 / Re^2 (2^(hc / ha)): then t = 2^(ha log2 s) needs no added
+  // constant, and t / R^2 = S 2^((ha - 1) log2 s) gives h without a
+  // reciprocal (one transcendental fewer per pixel; S goes into the folded
+  // factor of the x0, y0, e1, e2 columns, log2 S into the n column's
+  // constant).  The FP64 instance (the adjoint's; its exp2 costs more than
+  // its reciprocal) renders as pixel() does, with the factors k7 and k4 in
+  // the columns, and sums J^T J only when asked for.
+  constexpr bool kF32Mom = kMom && sizeof(T) == 4;
   T mS = (T)1, mFloor = A::kR2Floor, mHam1 = (T)0, mK5b = (T)0;
-  if constexpr (kMom) {
+  if constexpr (kF32Mom) {
     const T lS = A::uni(t.hc * A::rcp(t.ha));
     mS = A::uni(A::ex2(lS));
     mFloor = A::uni(A::kR2Floor * mS);
@@ -476,15 +482,23 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     const bool floored = s2 < mFloor;
     s2 = floored ? mFloor : s2;
     const T L = A::lg2(s2);
-    const T tr = A::ex2(L * mHam1);   // t / s
-    const T tt = tr * s2;
-    const T m0 = A::ex2(t.nb2 * tt);
-    const T c = m0 * tt;
-    T h = m0 * tr;                      // h / S
+    T m0, c, h;
+    if constexpr (kF32Mom) {
+      const T tr = A::ex2(L * mHam1);   // t / s
+      const T tt = tr * s2;
+      m0 = A::ex2(t.nb2 * tt);
+      c = m0 * tt;
+      h = m0 * tr;                      // h / S
+    } else {
+      const T tt = A::ex2(A::fma(L, t.ha, t.hc));
+      m0 = A::ex2(t.nb2 * tt);
+      c = m0 * tt;
+      h = c * A::rcp(s2) * t.k7;
+    }
     h = floored ? (T)0 : h;
     T J[8];
-    J[4] = c;
-    if constexpr (has(EM, 5)) J[5] = c * A::fma(L, t.k5a, mK5b);
+    J[4] = kF32Mom ? c : c * t.k4;
+    if constexpr (has(EM, 5)) J[5] = c * A::fma(L, t.k5a, kF32Mom ? mK5b : t.k5b);
     J[6] = m0;
     J[7] = (T)1;
     const T r = d - A::fma(t.I0, m0, t.sky);
@@ -492,31 +506,44 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     H[0] = h;
 #pragma unroll
     for (int j = 1; j < kMomN; ++j) H[j] = H[j - 1] * u2;
-    c2p = first ? r * r : A::fma(r, r, c2p);
+    if constexpr (kFlush > 0) {
+      c2p = first ? r * r : A::fma(r, r, c2p);
 #pragma unroll
-    for (int j = 0; j < kMomN; ++j) gq[j] = first ? H[j] * r : A::fma(H[j], r, gq[j]);
+      for (int j = 0; j < kMomN; ++j) gq[j] = first ? H[j] * r : A::fma(H[j], r, gq[j]);
+    } else {
+      acc.c2 = fma((double)r, (double)r, acc.c2);
 #pragma unroll
-    for (int s = 0; s < 2 * kMomN - 1; ++s) {
-      const int i = s < kMomN ? s : kMomN - 1, j = s - i;   // H_i H_j, i + j = s
-      mM[s] = A::fma(H[i], H[j], mM[s]);
+      for (int j = 0; j < kMomN; ++j) gm[j] = fma((double)H[j], (double)r, gm[j]);
+    }
+    if constexpr (JTJ) {
+#pragma unroll
+      for (int s = 0; s < 2 * kMomN - 1; ++s) {
+        const int i = s < kMomN ? s : kMomN - 1, j = s - i;   // H_i H_j, i + j = s
+        mM[s] = A::fma(H[i], H[j], mM[s]);
+      }
     }
 #pragma unroll
     for (int a = 4; a < 8; ++a) {
       if (!has(EM, a)) continue;
-      gp[a] = (a == 7) ? (first ? r : gp[a] + r) : (first ? J[a] * r : A::fma(J[a], r, gp[a]));
+      if constexpr (kFlush > 0)
+        gp[a] = (a == 7) ? (first ? r : gp[a] + r) : (first ? J[a] * r : A::fma(J[a], r, gp[a]));
+      else
+        acc.g[a] = (a == 7) ? acc.g[a] + (double)r : fma((double)J[a], (double)r, acc.g[a]);
+      if constexpr (JTJ) {
 #pragma unroll
-      for (int j = 0; j < kMomN; ++j)
-        if (a == 7)
-          mY[j] += H[j];
-        else
-          mX[a - 4][j] = A::fma(H[j], J[a], mX[a - 4][j]);
+        for (int j = 0; j < kMomN; ++j)
+          if (a == 7)
+            mY[j] += H[j];
+          else
+            mX[a - 4][j] = A::fma(H[j], J[a], mX[a - 4][j]);
 #pragma unroll
-      for (int c2 = a; c2 < 8; ++c2) {
-        if (!has(EM, c2) || (c2 == 7 && a == 7)) continue;
-        if (c2 == 7)
-          acc.A[tri(a, c2)] += J[a];
-        else
-          acc.A[tri(a, c2)] = A::fma(J[a], J[c2], acc.A[tri(a, c2)]);
+        for (int c2 = a; c2 < 8; ++c2) {
+          if (!has(EM, c2) || (c2 == 7 && a == 7)) continue;
+          if (c2 == 7)
+            acc.A[tri(a, c2)] += J[a];
+          else
+            acc.A[tri(a, c2)] = A::fma(J[a], J[c2], acc.A[tri(a, c2)]);
+        }
       }
     }
   };
@@ -629,33 +656,37 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
           for (int v = 0; v < 3; ++v) x[v] = fma(C[a][j], X[v][j], x[v]);
         }
         acc.g[a] = g;
-        if (has(EM, 7)) acc.A[tri(a, 7)] = (T)y;
+        if constexpr (JTJ) {
+          if (has(EM, 7)) acc.A[tri(a, 7)] = (T)y;
 #pragma unroll
-        for (int v = 0; v < 3; ++v)
-          if (has(EM, 4 + v)) acc.A[tri(a, 4 + v)] = (T)x[v];
-      }
-      // P[c][i] = sum_j C[c][j] M[i + j]; entry (a, c) = sum_i C[a][i] P[c][i]
-      double P[4][3];
-#pragma unroll
-      for (int c2 = 0; c2 < 4; ++c2) {
-        const int dc = c2 < 2 ? 2 : 3;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          double q = 0.0;
-#pragma unroll
-          for (int j = 0; j < dc; ++j) q = fma(C[c2][j], M[i + j], q);
-          P[c2][i] = q;
+          for (int v = 0; v < 3; ++v)
+            if (has(EM, 4 + v)) acc.A[tri(a, 4 + v)] = (T)x[v];
         }
       }
+      // P[c][i] = sum_j C[c][j] M[i + j]; entry (a, c) = sum_i C[a][i] P[c][i]
+      if constexpr (JTJ) {
+        double P[4][3];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int da = a < 2 ? 2 : 3;
+        for (int c2 = 0; c2 < 4; ++c2) {
+          const int dc = c2 < 2 ? 2 : 3;
 #pragma unroll
-        for (int c2 = a; c2 < 4; ++c2) {
-          double q = 0.0;
+          for (int i = 0; i < 3; ++i) {
+            double q = 0.0;
 #pragma unroll
-          for (int i = 0; i < da; ++i) q = fma(C[a][i], P[c2][i], q);
-          acc.A[tri(a, c2)] = (T)q;
+            for (int j = 0; j < dc; ++j) q = fma(C[c2][j], M[i + j], q);
+            P[c2][i] = q;
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int da = a < 2 ? 2 : 3;
+#pragma unroll
+          for (int c2 = a; c2 < 4; ++c2) {
+            double q = 0.0;
+#pragma unroll
+            for (int i = 0; i < da; ++i) q = fma(C[a][i], P[c2][i], q);
+            acc.A[tri(a, c2)] = (T)q;
+          }
         }
       }
     }

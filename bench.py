@@ -122,6 +122,32 @@ def counter_traffic(path, files, form=""):
             float(kv["write_kib" + sfx]) * float(kv["write_scale"])) * 1024.0
 
 
+def counter_kv(path, files):
+    """The key: value block of a committed counter summary, or None if it is
+    missing or the kernel's sources changed since the counters were taken."""
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    kv = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith("    "):
+            k, v = line.strip().split(":", 1)
+            kv[k.strip()] = v.strip()
+    return kv if kv.get("source_sha256_16") == sources_hash(files) else None
+
+
+VALU_FILE = os.path.join(ROOT, "profiles", "fit_sersic64h_valu.md")
+
+
+def fit_valu_issue(form):
+    """The 64 x 64 fit's measured VALU issue (wave64 instructions per SIMD per
+    four cycles, from its committed counters) for the given form, or None."""
+    kv = counter_kv(VALU_FILE, FIT_SOURCES)
+    v = kv.get("valu_issue_" + form) if kv else None
+    return float(v) if v is not None else None
+
+
 def fit_traffic_bytes(workload, form):
     """HBM bytes per launch of the fit of `workload` in the given form (None
     where no counters were taken for that pair)."""
@@ -419,6 +445,10 @@ def main():
                      "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
                      "traffic": fit_traffic_bytes(wl, chosen),
+                     "valu_issue": (fit_valu_issue(chosen) if wl == "sersic64h" else None),
+                     "valu_issue_unit": "wave64 VALU instructions per SIMD per 4 cycles "
+                                        "(SQ_INSTS_VALU / 1024 SIMDs / cycles x 4; 1 = one "
+                                        "instruction per pipe pass), from the committed counters",
                      "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "launch_ms": round(rc["fit_ms"], 4),
                      "flop_per_pixel_sweep": flop_px,

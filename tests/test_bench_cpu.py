@@ -54,3 +54,14 @@ def test_committed_counter_files_parse(workload):
     assert {"fetch_scale", "write_scale", "source_sha256_16"} <= keys
     assert any(k.startswith("fetch_kib") for k in keys)
     assert any(k.startswith("write_kib") for k in keys)
+
+
+def test_committed_valu_summary_parses():
+    """The fit's VALU summary holds the issue rates bench.py reports, and they
+    are plausible (saturated issue reads about one instruction per pass)."""
+    text = open(bench.VALU_FILE).read()
+    kv = {ln.strip().split(":", 1)[0]: ln.strip().split(":", 1)[1].strip()
+          for ln in text.splitlines() if ln.startswith("    ") and ":" in ln}
+    for form in ("plain", "f16"):
+        assert 0.5 < float(kv["valu_issue_" + form]) < 2.0
+    assert "source_sha256_16" in kv

@@ -223,6 +223,20 @@ int shape_chi2_bwd(const shape_batch* batch, const float* params, const float* g
                    float* chi2, float* grad_p, float* jtj, float* jtr, void* stream);
 
 /*
+ * The chain rule after the adjoint: the gradient above is linear in the
+ * upstream dL/dchi2 (Sec. 4.1, eq. chi2: chi^2 is the only function of the
+ * pixels it scales), so a caller that took grad_unit from shape_chi2_bwd with
+ * grad_chi2 = NULL (dL/dchi2 = 1; a forward pass that also takes the
+ * gradient) forms grad_p[i][k] = grad_chi2[i] * grad_unit[i][k] later
+ * without another sweep.
+ *   grad_unit [n][8] in (device), grad_chi2 [n] in or NULL (a copy),
+ *   grad_p [n][8] out; grad_p may equal grad_unit (in place).
+ * Returns SHAPE_EINVAL for n < 0 or a missing array (n > 0).
+ */
+int shape_chi2_grad_scale(const float* grad_unit, const float* grad_chi2, int64_t n,
+                          float* grad_p, void* stream);
+
+/*
  * Star sizes from weighted moments (Sec. 4.2).  About the centre and
  * ellipticity in rec (from shape_moments), with R the elliptical radius of
  * the model and f = I - sky0, each step forms r0 = sum f W, r2 = sum f W R^2,

@@ -124,6 +124,8 @@ def _load():
     lib.shape_chi2_fwd.restype = C.c_int
     lib.shape_chi2_bwd.argtypes = [bp, vp, vp, vp, vp, vp, vp, vp]
     lib.shape_chi2_bwd.restype = C.c_int
+    lib.shape_chi2_grad_scale.argtypes = [vp, vp, C.c_int64, vp, vp]
+    lib.shape_chi2_grad_scale.restype = C.c_int
     lib.shape_star_moments.argtypes = [bp, C.c_int32, vp, C.c_double, C.c_int32, vp, vp, vp, vp]
     lib.shape_star_moments.restype = C.c_int
     lib.shape_star_moments_beta.argtypes = [bp, C.c_double, vp, C.c_double, C.c_int32, vp, vp, vp,
@@ -396,22 +398,47 @@ def chi2_bwd(batch: DeviceBatch, params: torch.Tensor, grad_chi2: torch.Tensor |
     return dict(grad=grad, chi2=chi2, jtj=jtj, jtr=jtr)
 
 
+def chi2_grad_scale(grad_unit: torch.Tensor, grad_chi2: torch.Tensor | None = None,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """shape_chi2_grad_scale: grad [n, 8] = grad_chi2 [n] x grad_unit [n, 8]
+    (grad_unit taken by chi2_bwd with grad_chi2 = None)."""
+    dev = grad_unit.device
+    if (grad_unit.dtype != torch.float32 or grad_unit.dim() != 2 or grad_unit.shape[1] != 8
+            or not grad_unit.is_contiguous()):
+        raise ValueError("grad_unit must be a contiguous float32 [n, 8] tensor")
+    n = int(grad_unit.shape[0])
+    if grad_chi2 is not None:
+        grad_chi2 = grad_chi2.to(device=dev, dtype=torch.float32).contiguous()
+        if grad_chi2.numel() != n:
+            raise ValueError("grad_chi2 must hold one value per stamp")
+    if out is None:
+        out = torch.empty_like(grad_unit)
+    elif out.shape != grad_unit.shape or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 [n, 8] tensor")
+    _check(lib.shape_chi2_grad_scale(_ptr(grad_unit), _ptr(grad_chi2), n, _ptr(out),
+                                     _stream(dev)), "shape_chi2_grad_scale")
+    return out
+
+
 class SersicChi2(torch.autograd.Function):
-    """chi^2 of the model per stamp, differentiable in the parameters; the
-    backward is the library's adjoint sweep."""
+    """chi^2 of the model per stamp, differentiable in the parameters.  When
+    the parameters need a gradient, the forward pass is the library's adjoint
+    sweep with dL/dchi2 = 1 (chi^2 and the gradient in one sweep) and the
+    backward pass only scales that gradient by the upstream dL/dchi2;
+    otherwise the forward pass sweeps chi^2 alone."""
 
     @staticmethod
     def forward(ctx, params, batch):
-        chi2 = chi2_fwd(batch, params.detach().contiguous())
-        ctx.save_for_backward(params)
-        ctx.batch = batch
-        return chi2
+        p = params.detach().contiguous()
+        if ctx.needs_input_grad[0]:
+            out = chi2_bwd(batch, p)
+            ctx.grad_unit = out["grad"]
+            return out["chi2"]
+        return chi2_fwd(batch, p)
 
     @staticmethod
     def backward(ctx, grad_chi2):
-        (params,) = ctx.saved_tensors
-        out = chi2_bwd(ctx.batch, params.detach().contiguous(), grad_chi2)
-        return out["grad"], None
+        return chi2_grad_scale(ctx.grad_unit, grad_chi2), None
 
 
 def sersic_chi2(params: torch.Tensor, batch: DeviceBatch) -> torch.Tensor:

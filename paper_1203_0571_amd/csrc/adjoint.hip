@@ -113,7 +113,26 @@ hipError_t launch_forms(const shape_batch& b, const float* params, const float* 
   return launch_dt<DT, true, false>(b, params, grad_chi2, chi2, grad_p, jtj, jtr, stream);
 }
 
+// grad_p = grad_chi2 (per stamp) x grad_unit, eight entries per stamp.
+__global__ __launch_bounds__(256) void grad_scale_kernel(const float* grad_unit,
+                                                        const float* grad_chi2, int64_t n,
+                                                        float* grad_p) {
+  const int64_t m = n * 8;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    grad_p[i] = grad_chi2 ? grad_chi2[i >> 3] * grad_unit[i] : grad_unit[i];
+}
+
 }  // namespace
+
+hipError_t launch_grad_scale(const float* grad_unit, const float* grad_chi2, int64_t n,
+                             float* grad_p, hipStream_t stream) {
+  const int64_t blocks = (n * 8 + 255) / 256;
+  const unsigned grid = (unsigned)(blocks < 65536 ? blocks : 65536);
+  hipLaunchKernelGGL(grad_scale_kernel, dim3(grid), dim3(256), 0, stream, grad_unit, grad_chi2, n,
+                     grad_p);
+  return hipGetLastError();
+}
 
 hipError_t launch_chi2(const shape_batch& b, const float* params, const float* grad_chi2,
                        float* chi2, float* grad_p, float* jtj, float* jtr, bool grad,

@@ -175,6 +175,14 @@ int shape_chi2_bwd(const shape_batch* b, const float* params, const float* grad_
       launch_chi2(*b, params, grad_chi2, chi2, grad_p, jtj, jtr, true, (hipStream_t)stream));
 }
 
+int shape_chi2_grad_scale(const float* grad_unit, const float* grad_chi2, int64_t n,
+                          float* grad_p, void* stream) {
+  if (n < 0) return SHAPE_EINVAL;
+  if (n == 0) return SHAPE_OK;
+  if (!grad_unit || !grad_p) return SHAPE_EINVAL;
+  return from_hip(launch_grad_scale(grad_unit, grad_chi2, n, grad_p, (hipStream_t)stream));
+}
+
 int shape_star_moments(const shape_batch* b, int32_t profile, const float* rec, double tol,
                        int32_t max_iter, float* out, int32_t* iters, uint32_t* status,
                        void* stream) {

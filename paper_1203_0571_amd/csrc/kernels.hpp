@@ -75,5 +75,7 @@ hipError_t launch_frame_cut(const shape_frames& f, const int32_t* box, const int
 hipError_t launch_chi2(const shape_batch& b, const float* params, const float* grad_chi2,
                        float* chi2, float* grad_p, float* jtj, float* jtr, bool grad,
                        hipStream_t stream);
+hipError_t launch_grad_scale(const float* grad_unit, const float* grad_chi2, int64_t n,
+                             float* grad_p, hipStream_t stream);
 
 }  // namespace shape

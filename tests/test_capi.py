@@ -128,6 +128,10 @@ def test_chi2_argument_errors(shape):
     e = _batch(shape, n=0, pixels=None, sigma=None)
     assert L.shape_chi2_fwd(C.byref(e), None, None, None) == shape.OK
     assert L.shape_chi2_bwd(C.byref(e), None, None, None, None, None, None, None) == shape.OK
+    assert L.shape_chi2_grad_scale(out, None, -1, out, None) == shape.EINVAL
+    assert L.shape_chi2_grad_scale(None, None, 4, out, None) == shape.EINVAL
+    assert L.shape_chi2_grad_scale(out, None, 4, None, None) == shape.EINVAL
+    assert L.shape_chi2_grad_scale(None, None, 0, None, None) == shape.OK
 
 
 def test_queue_argument_errors(shape):

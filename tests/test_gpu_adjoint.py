@@ -108,10 +108,27 @@ def test_autograd_function(shape):
     db = shape.DeviceBatch.from_host(b, "cuda:0")
     p = torch.from_numpy(_params_away_from_optimum(b).astype(np.float32)).cuda().requires_grad_(True)
     w = torch.linspace(0.5, 1.5, b.n, device="cuda")
-    loss = (shape.sersic_chi2(p, db) * w).sum()
+    chi2 = shape.sersic_chi2(p, db)
+    loss = (chi2 * w).sum()
     (grad,) = torch.autograd.grad(loss, p)
-    direct = shape.chi2_bwd(db, p.detach(), w)["grad"]
-    torch.testing.assert_close(grad, direct, rtol=0, atol=0)
+    # the forward pass took chi^2 and the unit gradient in one adjoint sweep;
+    # the backward pass scaled the FP32 unit gradient by dL/dchi2 = w (one
+    # more FP32 rounding than the sweep's own FP64 scaling: 2 x 2^-24)
+    direct = shape.chi2_bwd(db, p.detach(), w)
+    torch.testing.assert_close(grad, direct["grad"], rtol=2.5e-7, atol=1e-30)
+    torch.testing.assert_close(chi2.detach(), direct["chi2"], rtol=0, atol=0)
+    # without a gradient the forward pass is the chi^2 sweep alone
+    with torch.no_grad():
+        plain = shape.sersic_chi2(p, db)
+    torch.testing.assert_close(plain, shape.chi2_fwd(db, p.detach()), rtol=0, atol=0)
+    torch.testing.assert_close(plain, chi2.detach(), rtol=1e-6, atol=0)
+    # the scale entry point: in place, and a copy without dL/dchi2
+    unit = shape.chi2_bwd(db, p.detach())["grad"]
+    torch.testing.assert_close(shape.chi2_grad_scale(unit), unit, rtol=0, atol=0)
+    scaled = shape.chi2_grad_scale(unit.clone(), w)
+    torch.testing.assert_close(scaled, unit * w[:, None], rtol=0, atol=0)
+    shape.chi2_grad_scale(unit, w, out=unit)
+    torch.testing.assert_close(unit, scaled, rtol=0, atol=0)
 
 
 def test_bad_parameters_give_nan(shape):

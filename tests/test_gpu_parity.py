@@ -105,6 +105,43 @@ def test_row_layout_8_params_small_sides(shape, side):
     check_fit(r, 0.8)
 
 
+def test_fit_from_pixel_centred_start(shape):
+    """Fits started with the centre exactly on a pixel centre: the first sweep
+    meets R^2 = 0 there (the floor, with the shape columns' factor h set to
+    zero) in the row layout's moment form.  Every fit stays finite, and the
+    fits agree with the oracle's fits from the same starting points by the
+    bars, or end at a validated minimum of the oracle's chi^2."""
+    import torch
+    b = synth.make("sersic64", count=64)
+    p0 = b.truth.astype(np.float64).copy()
+    p0[:, :2] = np.round(p0[:, :2])
+    db = shape.DeviceBatch.from_host(b, "cuda:0")
+    out = shape.fit_sersic(db, p_init=torch.from_numpy(p0.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items() if hasattr(v, "cpu")}
+    assert np.isfinite(g["p"]).all() and np.isfinite(g["chi2"]).all()
+    assert ((g["status"] & shape.ST_NONFINITE_INPUT) == 0).all()
+    pix = b.dequantised_f64()
+    o = oracle.opts(tol_lm=1e-9, max_iter_lm=200)
+    both = 0
+    for s in range(b.n):
+        img = pix[b.offsets[s]:b.offsets[s] + 64 * 64].reshape(64, 64)
+        ref = oracle.fit(img, float(b.sigma[s]), p0[s].astype(np.float32).astype(np.float64), o=o)
+        if not (g["status"][s] & shape.ST_CONVERGED and ref["status"] & oracle.CONVERGED):
+            continue
+        if (g["status"][s] | ref["status"]) & oracle.AT_BOUND:
+            continue
+        both += 1
+        pg = g["p"][s].astype(np.float64)
+        inside = (np.abs(pg[:2] - ref["p"][:2]).max() <= BAR_X and
+                  np.abs(pg[2:4] - ref["p"][2:4]).max() <= BAR_E and
+                  np.abs(pg[4:6] / ref["p"][4:6] - 1).max() <= BAR_REL)
+        if not inside:
+            assert validate_minimum(img, float(b.sigma[s]), 0, pg, ref["chi2"],
+                                    list(range(8)))[0], s
+    assert both >= 56, both
+
+
 def test_standard_error_stop_only_adds_convergence(shape):
     """The stop on steps below tol_sigma standard errors is an extra way to
     converge: every stamp that converges without it converges with it (the

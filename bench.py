@@ -880,7 +880,7 @@ def bench_adjoint(args):
                                                              "backward_jtj") / ALU_PEAK_TFLOPS, 4)}}}
     if not args.no_cpu:
         import oracle
-        m = min(2048, b.n)
+        m = min(65536, b.n)   # ~13 s of oracle work on one thread
         t = time.perf_counter()
         for s_ in range(m):
             oracle.chi2(b.stamp(s_), float(b.sigma[s_]), p[s_].astype(np.float32).astype(np.float64),

@@ -631,10 +631,14 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
       // the column sums from the moments, per lane, in FP64: column k is
       // h sum_j C[k][j] u2^j (degree 1 for x0, y0, 2 for e1, e2)
       flush();
-      const double C[4][3] = {{(double)c3, (double)t.n12, 0.0},
-                              {(double)c4, (double)t.n22, 0.0},
-                              {(double)p2c, (double)p2b, (double)t.p2a},
-                              {(double)p3c, (double)p3b, (double)t.p3a}};
+      // the FP32 instance folds the factor k7 S of these columns (and k4 of
+      // the Re column) in here, not into the sums afterwards
+      const double f7 = kF32Mom ? (double)(t.k7 * mS) : 1.0;
+      const double f4 = kF32Mom ? (double)t.k4 : 1.0;
+      const double C[4][3] = {{c3 * f7, t.n12 * f7, 0.0},
+                              {c4 * f7, t.n22 * f7, 0.0},
+                              {p2c * f7, p2b * f7, t.p2a * f7},
+                              {p3c * f7, p3b * f7, t.p3a * f7}};
       double M[5], X[3][3], Y[3];
 #pragma unroll
       for (int s = 0; s < 5; ++s) M[s] = (double)mM[s];
@@ -642,7 +646,7 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
       for (int j = 0; j < 3; ++j) {
         Y[j] = (double)mY[j];
 #pragma unroll
-        for (int v = 0; v < 3; ++v) X[v][j] = (double)mX[v][j];
+        for (int v = 0; v < 3; ++v) X[v][j] = (double)mX[v][j] * (v == 0 ? f4 : 1.0);
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
@@ -801,11 +805,12 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
   flush();
   if constexpr (kFold) {
     // the folded constant factors: column a of J is s_a times what was summed
-    const T k7 = kMom ? t.k7 * mS : t.k7;   // the moment form's h is h / S
-    const T sc[8] = {k7, k7, k7, k7, t.k4, (T)1, (T)1, (T)1};
+    // (the moment form folded them into its recombination, but for the
+    // Re column's sums among the Re, n, I0 and sky columns)
+    const T sc[8] = {t.k7, t.k7, t.k7, t.k7, t.k4, (T)1, (T)1, (T)1};
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
-      if (!has(EM, a)) continue;
+      if (!has(EM, a) || (kMom && a < 4)) continue;
       acc.g[a] *= (double)sc[a];
 #pragma unroll
       for (int c = a; c < 8; ++c)

@@ -324,11 +324,13 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-// Sersic b(n) and db/dn from the generated Chebyshev table (FP64 series; the
-// interval variable comes from the hardware log2, which is accurate to the
-// FP32 level the sweep uses b at).
+// Sersic b(n) and db/dn from the generated Chebyshev table in FP64 (the FP64
+// sweep of the adjoint).  The interval variable ln n is taken in FP64: from
+// the FP32 hardware log2, b(n) was off by up to 5e-8 relative, which moved
+// the FP64 gradient by up to 4e-5 of its scale on 32 x 32 Gaussian stamps
+// (b t reaches ~10 inside the stamp).
 __device__ inline void sersic_bn(double n, double* b, double* db) {
-  double x = (double)__builtin_amdgcn_logf((float)n) * kLn2;
+  double x = log(n);
   double t = (x - kBnLogLo) / (kBnLogHi - kBnLogLo) * kBnIntervals;
   // clamp in floating point first (fmin/fmax drop a NaN), so k is always a
   // valid interval; outside [0.2, 10] the series is extrapolated

@@ -49,7 +49,8 @@ def _check_grad(g_gpu, g_ref, p, sigma, rtol=1e-4):
     return float(err.max())
 
 
-@pytest.mark.parametrize("workload,count", [("sersic64", 256), ("uneven", 256), ("sersic64h", 128)])
+@pytest.mark.parametrize("workload,count", [("sersic64", 256), ("uneven", 256), ("sersic64h", 128),
+                                            ("plain32", 256)])
 def test_chi2_and_gradient_vs_oracle(shape, workload, count):
     import torch
     b = synth.make(workload, count=count)
@@ -75,7 +76,11 @@ def test_chi2_and_gradient_vs_oracle(shape, workload, count):
     assert np.abs(c2_gpu / c2_ref - 1).max() < 2e-5
     err = _check_grad(g_gpu, g_ref, p, b.sigma)
     print(workload, "max scaled gradient error vs oracle %.2e" % err)
-    assert err < 1e-4
+    assert err < 1e-4   # the benchmark's bar
+    # the FP64 sweep's gradient is exact to the rounding of its FP32 output
+    # (2^-24 ~ 6e-8); 1e-6 still catches an FP32-accurate constant (b(n) from
+    # the FP32 log gave 4e-5 on the 32 x 32 Gaussians)
+    assert err < 1e-6
     rel = np.abs(jtj_gpu - jtj_ref) / np.maximum(np.abs(jtj_ref), 1e-6 * np.abs(jtj_ref).max(1, keepdims=True))
     assert rel.max() < 1e-4
 

@@ -569,9 +569,9 @@ __device__ __forceinline__ void sweep(const shape_batch& b, const Stamp& st, con
     // on 262,144 64 x 64 stamps: fit 23.1 -> 20.8 ms, 32 x 32 4-parameter fit
     // 3.72 -> 2.83 ms; FP64 chi^2 0.74 -> 0.72 ms, with J^T J 1.47 -> 1.33 ms
     // (65,536 stamps).  FP16 stamps staged in LDS ran 5% slower unrolled (4%
-    // in the moment form: 18.1 vs 17.5 ms) and keep the loop, as does the FP64 gradient without J^T J, whose five waves
-    // per SIMD leave the unrolled run too few registers (136 spilled, 4x
-    // slower).
+    // in the moment form: 18.1 vs 17.5 ms) and keep the loop, as does the
+    // FP64 gradient without J^T J, whose five waves per SIMD leave the
+    // unrolled run too few registers (136 spilled, 4x slower).
     constexpr int kRun = 8;
     static_assert(kFlush == 0 || kFlush == kRun, "a run is one partial-sum block");
     constexpr bool kUnroll = DT == SHAPE_F32 && (sizeof(T) == 4 || EM == 0u || JTJ);

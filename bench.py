@@ -418,7 +418,9 @@ def main():
     wl_desc = ("sersic64h: 262,144 x 64x64 Sersic stamps, seed 0" if wl == "sersic64h" else
                "plain48: 100,000 x 48x48 Sersic stamps, seed 0")
     line = {
-        "metric": "objects fitted/sec (%dx%d Sersic stamps)" % (side, side),
+        "metric": ("objects fitted/sec (64\u00d764 S\u00e9rsic stamps), chosen vs plain form at "
+                   "fixed param error" if side == 64 else
+                   "objects fitted/sec (%dx%d Sersic stamps)" % (side, side)),
         "value": round(rc["objs"], 1),
         "unit": "objects/s",
         "n_gpus": 1,
